@@ -1,0 +1,211 @@
+/*
+ * pfsolve.h -- C ABI of the MI355X phase-field stepper.
+ *
+ * The library advances the grand-potential multi-phase-field model of
+ * Bauer et al., "Massively Parallel Phase-Field Simulations for Ternary
+ * Eutectic Directional Solidification" (SC'15, arXiv:1506.01684): N = 4
+ * order parameters phi (three solids, index 0..2, and the liquid, index 3)
+ * on the Gibbs simplex and K-1 = 2 chemical potentials mu on a regular 3D
+ * grid of equidistant cells (Sec. 2), with explicit Euler time steps made of
+ * a phi-sweep (Eqs. (1)-(2)) followed by a mu-sweep (Eqs. (3)-(4)) that reads
+ * mu_src, phi_src and phi_dst, then a swap of source and destination fields
+ * (Algorithm 1).  Temperature is frozen: T(z,t) = T0 + G (z + zoff - v t)
+ * (Sec. 2 and Sec. 3.3).  Boundaries: periodic in x and y, zero-flux mirror
+ * in z.  The initial state is solid Voronoi nuclei below a liquid (Sec. 2.1).
+ *
+ * Conventions shared by every call:
+ *  - No exception crosses the ABI; every fallible call returns pf_status and
+ *    on failure stores a message readable with pf_last_error() (per thread).
+ *  - Host arrays are always owned by the caller and copied in or out; host
+ *    field arrays are FP64, unpadded, x fastest: phi[a][z][y][x] (a = 0..3),
+ *    mu[i][z][y][x] (i = 0..1).
+ *  - Device memory is owned by the library unless the caller lends a buffer
+ *    (pf_device_buffer); a lent buffer must outlive the domain.
+ *  - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *    stream) and is asynchronous unless a call says it synchronises.
+ *  - Calls on different domains may run concurrently from different threads;
+ *    a single domain or pack is not re-entrant.
+ */
+#ifndef PFSOLVE_H
+#define PFSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_domain pf_domain; /* opaque: one grid and its fields */
+typedef struct pf_pack pf_pack;     /* opaque: many domains stepped together */
+
+typedef enum {
+  PF_OK = 0,
+  PF_ERR_INVALID_ARG = 1, /* a size, pointer or parameter is out of range */
+  PF_ERR_STATE = 2,       /* call made in the wrong order                 */
+  PF_ERR_UNSTABLE = 3,    /* explicit dt above the stability bound        */
+  PF_ERR_OOM = 4,         /* device allocation failed / buffer too small  */
+  PF_ERR_DEVICE = 5,      /* a HIP runtime call failed                    */
+  PF_ERR_NONFINITE = 6    /* diagnostics found NaN or Inf in the fields   */
+} pf_status;
+
+/* Storage and arithmetic precision of a domain.  PF_FP32 stores fields and
+ * evaluates the sweeps in FP32 with FP32 accumulation, but keeps the
+ * temperature, time, per-plane coefficients, the simplex projection and the
+ * diagnostic sums in FP64. */
+typedef enum { PF_FP64 = 0, PF_FP32 = 1 } pf_precision;
+
+typedef struct {
+  int32_t nx, ny, nz; /* cells per axis, each >= 1                         */
+  int32_t prec;       /* pf_precision                                      */
+  double dx;          /* cell spacing (> 0), the same on every axis (Sec. 2) */
+} pf_domain_desc;
+
+typedef struct {
+  void* base;   /* device pointer, 256-byte aligned                       */
+  size_t bytes; /* at least pf_required_bytes()                           */
+} pf_device_buffer;
+
+/* Model parameters (all FP64 on the host; copied by pf_set_params).
+ * Functional forms (the paper names the terms of Eqs. (1)-(4) but not their
+ * forms; these are the forms implemented):
+ *   gradient energy a = sum_{a<b} gamma_ab ac(q_ab)^2 |q_ab|^2,
+ *     q_ab = phi_a grad phi_b - phi_b grad phi_a,
+ *     ac(q) = 1 - delta_ab (3 - 4 sum_i (q_i/|q|)^4)   (cubic; 0 <= delta < 1/15)
+ *   obstacle omega = 16/pi^2 sum_{a<b} gamma_ab phi_a phi_b
+ *                    + gamma3 sum_{a<b<c} phi_a phi_b phi_c
+ *   grand potentials psi_a = -1/2 sum_i chi_ai(T) mu_i^2 - sum_i cbar_ai(T) mu_i
+ *                    + wbar_a(T), with chi = chi0 + chi1 (T-TE),
+ *                    cbar = c0 + c1 (T-TE), wbar = w0 + w1 (T-TE)
+ *   interpolation h_a = phi_a^2 / sum_b phi_b^2; mobility sum_a D_a phi_a chi_ai */
+typedef struct {
+  double eps;             /* interface width parameter (> 0)               */
+  double tau[4];          /* relaxation parameters (> 0)                   */
+  double gamma[4][4];     /* pair coefficients, symmetric, >= 0            */
+  double gamma3;          /* uniform triple coefficient (>= 0)             */
+  double aniso_delta[4][4]; /* cubic anisotropy per pair, symmetric        */
+  double chi0[4][2], chi1[4][2]; /* susceptibility coefficients            */
+  double c0[4][2], c1[4][2];     /* concentration offsets                  */
+  double w0[4], w1[4];           /* grand-potential offsets                */
+  double D[4];                   /* diffusivities (>= 0)                   */
+  double TE, T0, G, v, zoff;     /* T(z,t) = T0 + G (z + zoff - v t)       */
+  double dt;          /* <= 0: a quarter of the stability bound            */
+  int32_t antitrapping; /* 1: include the anti-trapping current of Eq. (4) */
+  int32_t mu_frozen;    /* 1: mu is held fixed (for tests of the phi part) */
+  int32_t diag_every;   /* run diagnostics every n steps inside pf_step (0 = never) */
+  int32_t reserved;
+} pf_params;
+
+typedef enum { PF_INIT_VORONOI = 0, PF_INIT_HOST = 1 } pf_init_kind;
+
+typedef struct {
+  int32_t kind;         /* pf_init_kind                                    */
+  int32_t nseeds;       /* VORONOI: number of 2D seeds (>= 0)              */
+  uint64_t seed;        /* VORONOI: SplitMix64 seed for seed positions     */
+  int32_t solid_height; /* VORONOI: cells with z < solid_height are solid  */
+  int32_t reserved;
+  double mu_init[2];    /* VORONOI: uniform initial mu                     */
+  const double* phi;    /* HOST: 4*nx*ny*nz values, layout as above        */
+  const double* mu;     /* HOST: 2*nx*ny*nz values                         */
+} pf_init;
+
+typedef struct {
+  double t;               /* time of the state the diagnostics describe   */
+  int64_t step;           /* its step index                               */
+  double sum_c[2];        /* sum over cells of c_i = sum_a h_a c_ai(mu,T) */
+  double sum_phi[4];      /* sum over cells of each phi_a                 */
+  double max_simplex_dev; /* max over cells of |sum_a phi_a - 1|           */
+  double phi_min, phi_max;
+  int64_t nonfinite;      /* cells holding a NaN or Inf in any field      */
+} pf_diag;
+
+/* Device bytes a domain needs (both field copies plus scratch). */
+pf_status pf_required_bytes(const pf_domain_desc* desc, size_t* out);
+
+/* Create a domain on the current HIP device.  borrowed: NULL = allocate.
+ * stream: a hipStream_t (NULL = null stream).  Errors: INVALID_ARG for
+ * sizes <= 0 or overflowing, OOM, DEVICE. */
+pf_status pf_create_domain(const pf_domain_desc* desc,
+                           const pf_device_buffer* borrowed, void* stream,
+                           pf_domain** out);
+
+/* Copy and validate parameters; resolve dt.  Errors: INVALID_ARG for
+ * non-positive eps/tau/dx, chi <= 0 over the domain's temperature range,
+ * negative gamma or D, delta outside [0, 1/15); UNSTABLE for an explicit dt
+ * above the stability bound min(dt_phi, dt_mu) with
+ * dt_phi = dx^2 min(tau) / (12 max(gamma) T_max (1+dmax)(1+15 dmax)) and
+ * dt_mu = dx^2 min(chi) / (6 max(D chi)). */
+pf_status pf_set_params(pf_domain* d, const pf_params* p);
+
+/* The resolved time step and the stability bound. */
+pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
+
+/* Initialise both sweeps' source fields; resets the step index to 0.
+ * VORONOI (Sec. 2.1): nseeds points drawn with SplitMix64 (Steele, Lea,
+ * Flood 2014) as (u nx, u ny), u = (next >> 11) 2^-53, x first; seed s gets
+ * solid phase s mod 3; each column takes the nearest seed by periodic
+ * minimum-image distance from its centre (i+1/2, j+1/2), lowest index on
+ * ties; z < solid_height is solid, the rest liquid; mu = mu_init.
+ * HOST: copy (and for FP32 round) the caller's arrays.  Synchronises. */
+pf_status pf_init_fields(pf_domain* d, const pf_init* init);
+
+/* Resume from a checkpoint: the next step is number `step`, t = step dt. */
+pf_status pf_set_time(pf_domain* d, int64_t step);
+
+/* Enqueue n time steps (Algorithm 1), asynchronously.  Errors: STATE when
+ * params or fields are missing; a pending NONFINITE from in-loop
+ * diagnostics is reported here or by pf_sync. */
+pf_status pf_step(pf_domain* d, int64_t n);
+
+/* As pf_step, and add the device time of each sweep, measured with HIP
+ * events on the domain's stream, to *phi_ms and *mu_ms (per-sweep totals
+ * over the n steps).  Synchronises at the end. */
+pf_status pf_step_timed(pf_domain* d, int64_t n, double* phi_ms,
+                        double* mu_ms);
+
+/* Wait for all enqueued work; report asynchronous errors. */
+pf_status pf_sync(pf_domain* d);
+
+/* Copy the current state to host (FP32 widened to FP64) and/or compute the
+ * diagnostics of the current state; any pointer may be NULL.  Synchronises.
+ * Returns NONFINITE (after filling the outputs) if the diagnostics count any
+ * non-finite cell. */
+pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag);
+
+/* Number of completed steps of the current state. */
+pf_status pf_get_step(const pf_domain* d, int64_t* step);
+
+/* Synchronise and free owned memory.  NULL is accepted. */
+void pf_destroy(pf_domain* d);
+
+/* Batched stepping (many independent domains of one precision).  Each pack
+ * step runs the per-plane coefficient kernel, the phi-sweep and the
+ * mu-sweep once each for all member domains, over a flattened list of
+ * (domain, tile) items; the step is captured once in a HIP graph and
+ * replayed.  Members keep their own sizes, parameters, time and step count. */
+pf_status pf_pack_create(int32_t prec, void* stream, int32_t max_domains,
+                         pf_pack** out);
+/* Add a domain (params and fields set, same precision) that should run
+ * nsteps more steps; takes effect at the next pf_pack_step. */
+pf_status pf_pack_add(pf_pack* pk, pf_domain* d, int64_t nsteps);
+/* Run `rounds` pack steps; a member that has run its steps idles.  Reports
+ * how many members have finished (they stay members until removed). */
+pf_status pf_pack_step(pf_pack* pk, int64_t rounds, int32_t* n_finished);
+/* Remaining steps of a member (0 = finished). */
+pf_status pf_pack_remaining(pf_pack* pk, const pf_domain* d, int64_t* left);
+pf_status pf_pack_remove(pf_pack* pk, pf_domain* d);
+pf_status pf_pack_sync(pf_pack* pk);
+void pf_pack_destroy(pf_pack* pk);
+
+/* Kernel variant used by subsequent sweeps of every domain: 0 = one thread
+ * per cell evaluating all six faces ("direct"), 1 = z-marching tiles that
+ * evaluate every face once and share it (default).  Both compute the same
+ * model; the tests hold both to the same tolerance. */
+pf_status pf_set_variant(int32_t variant);
+
+const char* pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFSOLVE_H */

@@ -1,0 +1,341 @@
+// pf_device.h -- device-side data structures and model arithmetic of the
+// phase-field stepper (Bauer et al., SC'15, arXiv:1506.01684).
+//
+// Model (Sec. 2): four order parameters phi_a on the Gibbs simplex (phases
+// 0..2 solid, 3 liquid), two chemical potentials mu_i, frozen temperature
+// T(z,t) = T0 + G (z + zoff - v t).  The phi equation (Eqs. (1)-(2)) is
+// discretised on cell faces: every face carries the normal component F_a of
+// da/d(grad phi_a) and its share S_a of da/dphi_a; the cell combines its six
+// faces.  The mu equation (Eq. (3)) is written in flux form: every face
+// carries Phi_i = M_i d mu_i - J_i with the anti-trapping current of Eq. (4);
+// the cell combines the divergence with exact-difference source terms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+constexpr int NP = 4;   // phases
+constexpr int NM = 2;   // chemical potentials
+constexpr int LQ = 3;   // liquid index
+constexpr int NPAIR = 6;
+constexpr int NFIELD = 6;  // phi_0..phi_3, mu_0, mu_1 in one copy
+
+// pair index of (a,b), a < b: (0,1)=0 (0,2)=1 (0,3)=2 (1,2)=3 (1,3)=4 (2,3)=5
+__host__ __device__ constexpr int pair_index(int a, int b) {
+  return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+}
+
+// Kernel-side parameters in the arithmetic type R.
+template <typename R>
+struct KParams {
+  R g1[NPAIR];     // gamma_ab
+  R g2[NPAIR];     // 2 gamma_ab
+  R g16[NPAIR];    // 16/pi^2 gamma_ab (pair part of d omega / d phi)
+  R delta[NPAIR];  // cubic anisotropy strength
+  R gamma3;        // triple coefficient
+  R rate[NP];      // dt / (tau_a eps)
+  R inv_dx, inv_4dx;
+  R dt, half_inv_dt;  // dt, 1/(2 dt)
+  R pieps4;           // pi eps / 4
+  int32_t aniso, antitrap, mu_frozen, pad;
+};
+
+// Per z-plane coefficients of one step, all evaluated in FP64 and then
+// rounded to R (Sec. 3.3: everything that depends only on the analytic
+// temperature is computed once per z slice).
+template <typename R>
+struct PlaneCoef {
+  R epsT, Toe;          // eps T, T/eps at T^n_k
+  R chi[NP][NM];        // chi_ai(T^n_k)
+  R cbar[NP][NM];       // cbar_ai(T^n_k)
+  R wbar[NP];           // omega_bar_a(T^n_k)
+  R Dchi[NP][NM];       // D_a chi_ai(T^n_k)          (x/y faces)
+  R dchiL[3][NM];       // chi_li - chi_ai at T^n_k    (x/y faces, a < 3)
+  R dcbL[3][NM];        // cbar_li - cbar_ai at T^n_k
+  R DchiZ[NP][NM];      // the same three at T^n_{k+1/2} (z face)
+  R dchiLZ[3][NM];
+  R dcbLZ[3][NM];
+  R chi1[NP][NM];       // chi_ai(T^{n+1}_k)
+  R dchi[NP][NM];       // chi(T^{n+1}_k) - chi(T^n_k)  (difference in FP64)
+  R dcbar[NP][NM];      // cbar(T^{n+1}_k) - cbar(T^n_k)
+};
+
+// Device-resident descriptor of one domain.
+struct DevDomain {
+  int32_t nx, ny, nz, pitch;  // cells; row stride in elements
+  int64_t plane, fstride;     // plane stride; field stride (elements)
+  int32_t tx, ty, zc;         // tile: tx * ty threads, zc planes per item
+  int32_t ntx, nty, nzc;      // tiles per axis
+  int32_t prec;               // 0 = FP64, 1 = FP32
+  int32_t active;             // set by the prologue for the current step
+  int64_t step;               // index n of the next step (state time n dt)
+  int32_t parity;             // copy that holds the current state
+  int32_t cur_src;            // prologue: source copy of the running step
+  int64_t cur_step;           // prologue: index of the running step
+  int64_t steps_left;         // < 0: unlimited
+  void* copy[2];              // base of each 6-field copy
+  void* coef;                 // PlaneCoef<R>[nz] of the running step
+  double dt, dx;
+  double eps, TE, T0, G, v, zoff;
+  double chi0[NP][NM], chi1[NP][NM], c0[NP][NM], c1[NP][NM];
+  double w0[NP], w1[NP], D[NP];
+  KParams<double> kp64;
+  KParams<float> kp32;
+};
+
+template <typename R>
+__device__ __forceinline__ const KParams<R>& kparams(const DevDomain& d);
+template <>
+__device__ __forceinline__ const KParams<double>& kparams<double>(const DevDomain& d) {
+  return d.kp64;
+}
+template <>
+__device__ __forceinline__ const KParams<float>& kparams<float>(const DevDomain& d) {
+  return d.kp32;
+}
+
+// ------------------------------------------------------------ math helpers
+
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double rsq_(double x) { return 1.0 / __builtin_sqrt(x); }
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double div_(double a, double b) { return a / b; }
+__device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// --------------------------------------------------------- phi face stage
+
+// Cubic-anisotropic pair term: X = d(ac(q)^2 |q|^2)/dq
+//   = 2 ac [ ac q + 16 delta |q| (qhat^3 - P qhat) ],  P = sum qhat_i^4,
+// with X = 2 q when delta = 0 or |q|^2 <= 1e-30.  Only the component along
+// the face normal D is needed.
+template <typename R, int D>
+__device__ __forceinline__ R aniso_Xd(R qx, R qy, R qz, R delta) {
+  const R q[3] = {qx, qy, qz};
+  R qq = qx * qx + qy * qy + qz * qz;
+  if (delta == R(0) || qq <= R(1e-30)) return R(2) * q[D];
+  R qn = sqrt_(qq);
+  R inv = rcp_(qn);
+  R hx = qx * inv, hy = qy * inv, hz = qz * inv;
+  R P = (hx * hx) * (hx * hx) + (hy * hy) * (hy * hy) + (hz * hz) * (hz * hz);
+  R ac = R(1) - delta * (R(3) - R(4) * P);
+  const R h[3] = {hx, hy, hz};
+  R hd = h[D];
+  return R(2) * ac * (ac * q[D] + R(16) * delta * qn * (hd * hd * hd - P * hd));
+}
+
+// Face stage of the phi-sweep on a face with normal D.
+//  pb[a]  face average of phi_a
+//  gn[a]  normal difference (phi_a,U - phi_a,L)/dx
+//  gt1/gt2 tangential components (only read when ANISO)
+// Outputs F_a = sum_{b!=a} gamma_ab (-pb_b) X_ab.e_D  and
+//         S_a = sum_{b!=a} gamma_ab  X_ab.e_D (gn_b),  X_ba = -X_ab.
+template <typename R, bool ANISO, int D>
+__device__ __forceinline__ void phi_face(const KParams<R>& P, const R pb[NP], const R gn[NP],
+                                         const R gt1[NP], const R gt2[NP], R F[NP], R S[NP]) {
+#pragma unroll
+  for (int a = 0; a < NP; ++a) F[a] = S[a] = R(0);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+#pragma unroll
+    for (int b = a + 1; b < NP; ++b) {
+      const int pi = pair_index(a, b);
+      R Y;  // gamma_ab X_ab.e_D
+      if constexpr (ANISO) {
+        // full generalised gradient q = pb_a grad phi_b - pb_b grad phi_a
+        R qn = pb[a] * gn[b] - pb[b] * gn[a];
+        R q1 = pb[a] * gt1[b] - pb[b] * gt1[a];
+        R q2 = pb[a] * gt2[b] - pb[b] * gt2[a];
+        R qx, qy, qz;
+        if constexpr (D == 0) { qx = qn; qy = q1; qz = q2; }
+        else if constexpr (D == 1) { qx = q1; qy = qn; qz = q2; }
+        else { qx = q1; qy = q2; qz = qn; }
+        Y = P.g1[pi] * aniso_Xd<R, D>(qx, qy, qz, P.delta[pi]);
+      } else {
+        Y = P.g2[pi] * (pb[a] * gn[b] - pb[b] * gn[a]);
+      }
+      F[a] -= pb[b] * Y;
+      F[b] += pb[a] * Y;
+      S[a] += Y * gn[b];
+      S[b] -= Y * gn[a];
+    }
+  }
+}
+
+// ------------------------------------------------------------ projection
+
+// Euclidean projection of y onto {x >= 0, sum x = 1} followed by
+// renormalisation, in FP64 (sort descending, largest j with
+// u_j - (s_j - 1)/j > 0, threshold theta = (s_rho - 1)/rho, clip).
+__device__ __forceinline__ void project_simplex(const double y[NP], double x[NP]) {
+  double u0 = y[0], u1 = y[1], u2 = y[2], u3 = y[3];
+  // sorting network, descending
+#define PF_CSWAP(a, b)        \
+  {                           \
+    double hi = fmax(a, b);   \
+    double lo = fmin(a, b);   \
+    a = hi;                   \
+    b = lo;                   \
+  }
+  PF_CSWAP(u0, u1);
+  PF_CSWAP(u2, u3);
+  PF_CSWAP(u0, u2);
+  PF_CSWAP(u1, u3);
+  PF_CSWAP(u1, u2);
+#undef PF_CSWAP
+  double s1 = u0, s2 = s1 + u1, s3 = s2 + u2, s4 = s3 + u3;
+  // rho = largest j whose condition holds (the conditions hold on a prefix)
+  double srho = s1, rinv = 1.0;
+  int rho = 1;
+  if (u1 - (s2 - 1.0) / 2.0 > 0.0) { rho = 2; srho = s2; }
+  if (u2 - (s3 - 1.0) / 3.0 > 0.0) { rho = 3; srho = s3; }
+  if (u3 - (s4 - 1.0) / 4.0 > 0.0) { rho = 4; srho = s4; }
+  (void)rinv;
+  double theta = (srho - 1.0) / (double)rho;
+  double xs[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    double v = y[a] - theta;
+    xs[a] = v > 0.0 ? v : 0.0;
+  }
+  double sum = ((xs[0] + xs[1]) + xs[2]) + xs[3];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) x[a] = xs[a] / sum;
+}
+
+// -------------------------------------------------------- phi cell stage
+
+// Cell stage of the phi-sweep (Eqs. (1)-(2)): A_a from the faces, the
+// obstacle derivative, the driving force (2 phi_a/S)(psi_a - sum h_b psi_b),
+// rhs_a = eps T A_a + (T/eps) omega'_a + psi'_a, Lagrange mean over the four
+// phases, explicit Euler, projection.
+template <typename R>
+__device__ __forceinline__ void phi_cell(const KParams<R>& P, const PlaneCoef<R>& C,
+                                         const R ph[NP], const R mu[NM], const R Ssum[NP],
+                                         const R Fdiff[NP], double out[NP]) {
+  // Ssum[a] = sum_d (S_up + S_low);  Fdiff[a] = sum_d (F_up - F_low)
+  R A[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) A[a] = R(0.5) * Ssum[a] - Fdiff[a] * P.inv_dx;
+  R S = ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2] + ph[3] * ph[3];
+  R invS = rcp_(S);
+  R psi[NP], psibar = R(0);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    R quad = C.chi[a][0] * mu[0] * mu[0] + C.chi[a][1] * mu[1] * mu[1];
+    R lin = C.cbar[a][0] * mu[0] + C.cbar[a][1] * mu[1];
+    psi[a] = R(-0.5) * quad - lin + C.wbar[a];
+    psibar += (ph[a] * ph[a]) * psi[a];
+  }
+  psibar *= invS;
+  R rhs[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    R dpsi = (R(2) * ph[a] * invS) * (psi[a] - psibar);
+    R pair = R(0), triple = R(0);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      if (b == a) continue;
+      pair += P.g16[a < b ? pair_index(a, b) : pair_index(b, a)] * ph[b];
+#pragma unroll
+      for (int e = b + 1; e < NP; ++e)
+        if (e != a) triple += ph[b] * ph[e];
+    }
+    R domega = pair + P.gamma3 * triple;
+    rhs[a] = C.epsT * A[a] + C.Toe * domega + dpsi;
+  }
+  R mean = R(0.25) * (((rhs[0] + rhs[1]) + rhs[2]) + rhs[3]);
+  double y[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) y[a] = (double)(ph[a] - P.rate[a] * (rhs[a] - mean));
+  project_simplex(y, out);
+}
+
+// --------------------------------------------------------- mu face stage
+
+// Face stage of the mu-sweep on a face with normal D (Eq. (3) flux and
+// Eq. (4) normal component):
+//   M_i = sum_a D_a pb_a chi_ai(T_f),  diff_i = M_i (mu_i,U - mu_i,L)/dx
+//   J_i = (pi eps/4) sum_{a<3} w_a rate_a (n_a.n_l)(n_a.e_D) dc_ai
+//   w_a = sqrt(pb_a pb_l) pb_l / sum pb^2  (= g_a h_l / sqrt(phi_a phi_l))
+//   (n_a.n_l)(n_a.e_D) = (g_a.g_l) g_a,D / (|g_a|^2 |g_l|), 0 if a gradient is 0
+//   dc_ai = (chi_li - chi_ai) mubar_i + (cbar_li - cbar_ai)
+// pb: face average of phi^n; gn/gt1/gt2: normal and tangential face
+// gradient of phi^n; dph: (phi^{n+1}-phi^n)_L + (...)_U per solid phase;
+// mL/mU: mu^n at the face cells.
+template <typename R, int D>
+__device__ __forceinline__ void mu_face(const KParams<R>& P, const R Dchi[NP][NM],
+                                        const R dchiL[3][NM], const R dcbL[3][NM],
+                                        const R pb[NP], const R gn[NP], const R gt1[NP],
+                                        const R gt2[NP], const R dph[3], const R mL[NM],
+                                        const R mU[NM], R Phi[NM]) {
+  R M0 = R(0), M1 = R(0);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    M0 += Dchi[a][0] * pb[a];
+    M1 += Dchi[a][1] * pb[a];
+  }
+  Phi[0] = M0 * (mU[0] - mL[0]) * P.inv_dx;
+  Phi[1] = M1 * (mU[1] - mL[1]) * P.inv_dx;
+  if (!P.antitrap) return;
+  const R mb0 = R(0.5) * (mL[0] + mU[0]), mb1 = R(0.5) * (mL[1] + mU[1]);
+  const R gl2 = gn[LQ] * gn[LQ] + gt1[LQ] * gt1[LQ] + gt2[LQ] * gt2[LQ];
+  if (!(gl2 > R(0))) return;
+  const R pl = pb[LQ];
+  const R Sb = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2] + pl * pl;
+  const R base = pl * rcp_(Sb) * rsq_(gl2) * P.half_inv_dt;
+  R J0 = R(0), J1 = R(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R prod = pb[a] * pl;
+    R ga2 = gn[a] * gn[a] + gt1[a] * gt1[a] + gt2[a] * gt2[a];
+    if (prod > R(0) && ga2 > R(0)) {
+      R dot = gn[a] * gn[LQ] + gt1[a] * gt1[LQ] + gt2[a] * gt2[LQ];
+      R coef = sqrt_(prod) * base * dph[a] * div_(dot * gn[a], ga2);
+      J0 += coef * (dchiL[a][0] * mb0 + dcbL[a][0]);
+      J1 += coef * (dchiL[a][1] * mb1 + dcbL[a][1]);
+    }
+  }
+  Phi[0] -= P.pieps4 * J0;
+  Phi[1] -= P.pieps4 * J1;
+}
+
+// ---------------------------------------------------------- mu cell stage
+
+// Cell stage of the mu-sweep: c^{n+1} - c^n = dt div(Phi) is solved for
+// mu^{n+1} with c = sum_a h_a (chi_a mu + cbar_a):
+//   src_i = sum_a (h1_a - h0_a)(chi_ai mu_i + cbar_ai - cbar_li)
+//         + sum_a h1_a (dchi_ai mu_i + dcbar_ai)
+//   mu_i^{n+1} = mu_i + (dt div_i - src_i) / sum_a h1_a chi_ai(T^{n+1})
+template <typename R>
+__device__ __forceinline__ void mu_cell(const KParams<R>& P, const PlaneCoef<R>& C,
+                                        const R p0[NP], const R p1[NP], const R mu[NM],
+                                        const R div[NM], R out[NM]) {
+  R S0 = p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2] + p0[3] * p0[3];
+  R S1 = p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2] + p1[3] * p1[3];
+  R i0 = rcp_(S0), i1 = rcp_(S1);
+  R h0[NP], h1[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    h0[a] = p0[a] * p0[a] * i0;
+    h1[a] = p1[a] * p1[a] * i1;
+  }
+#pragma unroll
+  for (int q = 0; q < NM; ++q) {
+    const R cref = C.cbar[LQ][q];
+    R src = R(0), chi = R(0);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      src += (h1[a] - h0[a]) * (C.chi[a][q] * mu[q] + (C.cbar[a][q] - cref)) +
+             h1[a] * (C.dchi[a][q] * mu[q] + C.dcbar[a][q]);
+      chi += h1[a] * C.chi1[a][q];
+    }
+    out[q] = mu[q] + div_(P.dt * div[q] - src, chi);
+  }
+}
+
+}  // namespace pfk

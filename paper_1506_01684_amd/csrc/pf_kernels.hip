@@ -1,0 +1,462 @@
+// pf_kernels.hip -- HIP kernels of the phase-field time step for gfx950.
+//
+// One step (Algorithm 1 of the paper) is three launches on one stream:
+//   prologue: per-plane temperature coefficients of the step in FP64
+//             (Sec. 3.3), choice of source/destination copy, step counter;
+//   phi-sweep: phi_dst <- (phi_src, mu_src)             (Eqs. (1)-(2));
+//   mu-sweep:  mu_dst  <- (mu_src, phi_src, phi_dst)     (Eqs. (3)-(4)).
+// Boundaries are applied by index arithmetic (periodic x/y, mirror z), so
+// there are no ghost layers and no separate boundary pass.
+//
+// This file holds the prologue, the "direct" variant of both sweeps (one
+// thread per cell evaluating all six faces), the Voronoi fill and the
+// diagnostics reduction.  The face-sharing z-marching variant is in
+// pf_tiled.hip.
+#include <hip/hip_runtime.h>
+
+#include "pf_device.h"
+#include "pf_kernels_common.h"
+#include "pf_launch.h"
+
+namespace pfk {
+
+// ------------------------------------------------------------- prologue
+
+// One work group per domain.  Evaluates the per-plane coefficients of step
+// n = d.step at t_n = n dt and t_{n+1} = (n+1) dt (products, never sums) in
+// FP64, rounds them to R, records the source copy, then advances the step
+// counter and the parity.  A domain whose step budget is spent is marked
+// inactive and left untouched.
+template <typename R>
+__global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, int ndom) {
+  DevDomain& d = *doms[blockIdx.x];
+  __shared__ int64_t s_step;
+  __shared__ int s_src, s_act;
+  if (threadIdx.x == 0) {
+    int act = d.steps_left != 0;
+    s_act = act;
+    s_step = d.step;
+    s_src = d.parity;
+  }
+  __syncthreads();
+  if (!s_act) {
+    if (threadIdx.x == 0) d.active = 0;
+    return;
+  }
+  const int64_t n = s_step;
+  const double t0 = (double)n * d.dt, t1 = (double)(n + 1) * d.dt;
+  PlaneCoef<R>* tab = static_cast<PlaneCoef<R>*>(d.coef);
+  for (int k = threadIdx.x; k < d.nz; k += blockDim.x) {
+    const double zc = (double)k * d.dx + d.zoff;
+    const double Tn = d.T0 + d.G * (zc - d.v * t0);
+    const double Tz = d.T0 + d.G * (zc + 0.5 * d.dx - d.v * t0);
+    const double Tn1 = d.T0 + d.G * (zc - d.v * t1);
+    PlaneCoef<R> c;
+    c.epsT = (R)(d.eps * Tn);
+    c.Toe = (R)(Tn / d.eps);
+    double chiN[NP][NM], cbN[NP][NM], chiZ[NP][NM], cbZ[NP][NM];
+    for (int a = 0; a < NP; ++a) {
+      c.wbar[a] = (R)(d.w0[a] + d.w1[a] * (Tn - d.TE));
+      for (int q = 0; q < NM; ++q) {
+        chiN[a][q] = d.chi0[a][q] + d.chi1[a][q] * (Tn - d.TE);
+        cbN[a][q] = d.c0[a][q] + d.c1[a][q] * (Tn - d.TE);
+        chiZ[a][q] = d.chi0[a][q] + d.chi1[a][q] * (Tz - d.TE);
+        cbZ[a][q] = d.c0[a][q] + d.c1[a][q] * (Tz - d.TE);
+        const double chiN1 = d.chi0[a][q] + d.chi1[a][q] * (Tn1 - d.TE);
+        const double cbN1 = d.c0[a][q] + d.c1[a][q] * (Tn1 - d.TE);
+        c.chi[a][q] = (R)chiN[a][q];
+        c.cbar[a][q] = (R)cbN[a][q];
+        c.Dchi[a][q] = (R)(d.D[a] * chiN[a][q]);
+        c.DchiZ[a][q] = (R)(d.D[a] * chiZ[a][q]);
+        c.chi1[a][q] = (R)chiN1;
+        c.dchi[a][q] = (R)(chiN1 - chiN[a][q]);
+        c.dcbar[a][q] = (R)(cbN1 - cbN[a][q]);
+      }
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int q = 0; q < NM; ++q) {
+        c.dchiL[a][q] = (R)(chiN[LQ][q] - chiN[a][q]);
+        c.dcbL[a][q] = (R)(cbN[LQ][q] - cbN[a][q]);
+        c.dchiLZ[a][q] = (R)(chiZ[LQ][q] - chiZ[a][q]);
+        c.dcbLZ[a][q] = (R)(cbZ[LQ][q] - cbZ[a][q]);
+      }
+    tab[k] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d.active = 1;
+    d.cur_step = n;
+    d.cur_src = s_src;
+    d.step = n + 1;
+    d.parity = s_src ^ 1;
+    if (d.steps_left > 0) d.steps_left -= 1;
+  }
+}
+
+// ------------------------------------------------------- direct variant
+
+// Gather the face inputs of the face between L=(xl,yl,zl) and U (normal D):
+// face averages pb, normal differences gn and, when FULL, the tangential
+// components gt1, gt2 (axes in increasing order, skipping D), each the
+// average of the central differences at L and U (4-point stencil).
+template <typename R, int D, bool FULL>
+__device__ __forceinline__ void gather_face(const R* const* f, const Geo& g, int xl, int yl,
+                                            int zl, R inv_dx, R inv_4dx, R pb[NP], R gn[NP],
+                                            R gt1[NP], R gt2[NP]) {
+  const int xu = D == 0 ? g.xp(xl) : xl;
+  const int yu = D == 1 ? g.yp(yl) : yl;
+  const int zu = D == 2 ? zl + 1 : zl;
+  const int64_t oL = g.at(xl, yl, zl), oU = g.at(xu, yu, zu);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    const R uL = f[a][oL], uU = f[a][oU];
+    pb[a] = R(0.5) * (uL + uU);
+    gn[a] = (uU - uL) * inv_dx;
+    gt1[a] = gt2[a] = R(0);
+  }
+  if constexpr (FULL) {
+    // tangential axes
+    constexpr int t1 = D == 0 ? 1 : 0;
+    constexpr int t2 = D == 2 ? 1 : 2;
+    int64_t o1[4], o2[4];  // L+, U+, L-, U-
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int tt = s == 0 ? t1 : t2;
+      int64_t* o = s == 0 ? o1 : o2;
+      if (tt == 0) {
+        o[0] = g.at(g.xp(xl), yl, zl); o[1] = g.at(g.xp(xu), yu, zu);
+        o[2] = g.at(g.xm(xl), yl, zl); o[3] = g.at(g.xm(xu), yu, zu);
+      } else if (tt == 1) {
+        o[0] = g.at(xl, g.yp(yl), zl); o[1] = g.at(xu, g.yp(yu), zu);
+        o[2] = g.at(xl, g.ym(yl), zl); o[3] = g.at(xu, g.ym(yu), zu);
+      } else {
+        o[0] = g.at(xl, yl, g.zp(zl)); o[1] = g.at(xu, yu, g.zp(zu));
+        o[2] = g.at(xl, yl, g.zm(zl)); o[3] = g.at(xu, yu, g.zm(zu));
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      gt1[a] = ((f[a][o1[0]] + f[a][o1[1]]) - (f[a][o1[2]] + f[a][o1[3]])) * inv_4dx;
+      gt2[a] = ((f[a][o2[0]] + f[a][o2[1]]) - (f[a][o2[2]] + f[a][o2[3]])) * inv_4dx;
+    }
+  }
+}
+
+template <typename R, bool ANISO, int D>
+__device__ __forceinline__ void phi_face_at(const KParams<R>& P, const R* const* f, const Geo& g,
+                                            int xl, int yl, int zl, R F[NP], R S[NP]) {
+  if (D == 2 && (zl < 0 || zl >= g.nz - 1)) {  // zero-flux z boundary
+#pragma unroll
+    for (int a = 0; a < NP; ++a) F[a] = S[a] = R(0);
+    return;
+  }
+  R pb[NP], gn[NP], gt1[NP], gt2[NP];
+  gather_face<R, D, ANISO>(f, g, xl, yl, zl, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+  phi_face<R, ANISO, D>(P, pb, gn, gt1, gt2, F, S);
+}
+
+template <typename R, bool ANISO>
+__global__ __launch_bounds__(kTileThreads) void phi_direct_kernel(DevDomain* const* doms,
+                                                                  const int32_t* first, int ndom,
+                                                                  int total) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int di = find_domain(first, ndom, item);
+    const DevDomain& d = *doms[di];
+    if (!d.active) continue;
+    const WorkTile w = decode_item(d, item - first[di], threadIdx.x);
+    if (!w.valid) continue;
+    const Geo g = make_geo(d);
+    const KParams<R>& P = kparams<R>(d);
+    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
+    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
+    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
+    const R* ph[NP] = {src, src + d.fstride, src + 2 * d.fstride, src + 3 * d.fstride};
+    const R* mu[NM] = {src + 4 * d.fstride, src + 5 * d.fstride};
+    const int x = w.x, y = w.y;
+    const int xm = g.xm(x), ym = g.ym(y);
+    for (int k = w.z0; k < w.z1; ++k) {
+      R Fu[NP], Su[NP], Fl[NP], Sl[NP], Ss[NP], Fd[NP];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) Ss[a] = Fd[a] = R(0);
+      phi_face_at<R, ANISO, 0>(P, ph, g, x, y, k, Fu, Su);
+      phi_face_at<R, ANISO, 0>(P, ph, g, xm, y, k, Fl, Sl);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) { Ss[a] += Su[a] + Sl[a]; Fd[a] += Fu[a] - Fl[a]; }
+      phi_face_at<R, ANISO, 1>(P, ph, g, x, y, k, Fu, Su);
+      phi_face_at<R, ANISO, 1>(P, ph, g, x, ym, k, Fl, Sl);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) { Ss[a] += Su[a] + Sl[a]; Fd[a] += Fu[a] - Fl[a]; }
+      phi_face_at<R, ANISO, 2>(P, ph, g, x, y, k, Fu, Su);
+      phi_face_at<R, ANISO, 2>(P, ph, g, x, y, k - 1, Fl, Sl);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) { Ss[a] += Su[a] + Sl[a]; Fd[a] += Fu[a] - Fl[a]; }
+      const int64_t o = g.at(x, y, k);
+      R pc[NP], mc[NM];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) pc[a] = ph[a][o];
+      mc[0] = mu[0][o];
+      mc[1] = mu[1][o];
+      double out[NP];
+      phi_cell<R>(P, tab[k], pc, mc, Ss, Fd, out);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) dst[a * d.fstride + o] = (R)out[a];
+    }
+  }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void mu_face_at(const KParams<R>& P, const PlaneCoef<R>& C,
+                                           const R* const* f0, const R* const* f1,
+                                           const R* const* mu, const Geo& g, int xl, int yl,
+                                           int zl, R Phi[NM]) {
+  if (D == 2 && (zl < 0 || zl >= g.nz - 1)) {
+    Phi[0] = Phi[1] = R(0);
+    return;
+  }
+  R pb[NP], gn[NP], gt1[NP], gt2[NP];
+  gather_face<R, D, true>(f0, g, xl, yl, zl, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+  const int xu = D == 0 ? g.xp(xl) : xl;
+  const int yu = D == 1 ? g.yp(yl) : yl;
+  const int zu = D == 2 ? zl + 1 : zl;
+  const int64_t oL = g.at(xl, yl, zl), oU = g.at(xu, yu, zu);
+  R dph[3], mL[NM], mU[NM];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dph[a] = (f1[a][oL] - f0[a][oL]) + (f1[a][oU] - f0[a][oU]);
+#pragma unroll
+  for (int q = 0; q < NM; ++q) { mL[q] = mu[q][oL]; mU[q] = mu[q][oU]; }
+  if (D == 2)
+    mu_face<R, D>(P, C.DchiZ, C.dchiLZ, C.dcbLZ, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+  else
+    mu_face<R, D>(P, C.Dchi, C.dchiL, C.dcbL, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kTileThreads) void mu_direct_kernel(DevDomain* const* doms,
+                                                                 const int32_t* first, int ndom,
+                                                                 int total) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int di = find_domain(first, ndom, item);
+    const DevDomain& d = *doms[di];
+    if (!d.active) continue;
+    const WorkTile w = decode_item(d, item - first[di], threadIdx.x);
+    if (!w.valid) continue;
+    const Geo g = make_geo(d);
+    const KParams<R>& P = kparams<R>(d);
+    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
+    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
+    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
+    const R* p0[NP] = {src, src + d.fstride, src + 2 * d.fstride, src + 3 * d.fstride};
+    const R* mu[NM] = {src + 4 * d.fstride, src + 5 * d.fstride};
+    const R* p1[NP] = {dst, dst + d.fstride, dst + 2 * d.fstride, dst + 3 * d.fstride};
+    R* mo[NM] = {dst + 4 * d.fstride, dst + 5 * d.fstride};
+    const int x = w.x, y = w.y;
+    const int xm = g.xm(x), ym = g.ym(y);
+    for (int k = w.z0; k < w.z1; ++k) {
+      const int64_t o = g.at(x, y, k);
+      if (P.mu_frozen) {
+        mo[0][o] = mu[0][o];
+        mo[1][o] = mu[1][o];
+        continue;
+      }
+      const PlaneCoef<R>& C = tab[k];
+      const PlaneCoef<R>& Cm = tab[k > 0 ? k - 1 : 0];
+      R div[NM] = {R(0), R(0)}, Pu[NM], Pl[NM];
+      mu_face_at<R, 0>(P, C, p0, p1, mu, g, x, y, k, Pu);
+      mu_face_at<R, 0>(P, C, p0, p1, mu, g, xm, y, k, Pl);
+      div[0] += Pu[0] - Pl[0];
+      div[1] += Pu[1] - Pl[1];
+      mu_face_at<R, 1>(P, C, p0, p1, mu, g, x, y, k, Pu);
+      mu_face_at<R, 1>(P, C, p0, p1, mu, g, x, ym, k, Pl);
+      div[0] += Pu[0] - Pl[0];
+      div[1] += Pu[1] - Pl[1];
+      mu_face_at<R, 2>(P, C, p0, p1, mu, g, x, y, k, Pu);
+      mu_face_at<R, 2>(P, Cm, p0, p1, mu, g, x, y, k - 1, Pl);
+      div[0] = (div[0] + (Pu[0] - Pl[0])) * P.inv_dx;
+      div[1] = (div[1] + (Pu[1] - Pl[1])) * P.inv_dx;
+      R c0[NP], c1[NP], mc[NM], out[NM];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) { c0[a] = p0[a][o]; c1[a] = p1[a][o]; }
+      mc[0] = mu[0][o];
+      mc[1] = mu[1][o];
+      mu_cell<R>(P, C, c0, c1, mc, div, out);
+      mo[0][o] = out[0];
+      mo[1][o] = out[1];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- fill
+
+template <typename R>
+__global__ __launch_bounds__(256) void fill_kernel(const DevDomain* dom, const int8_t* phase_map,
+                                                   int32_t solid_height, double mu0, double mu1) {
+  const DevDomain& d = *dom;
+  R* base = static_cast<R*>(d.copy[d.parity]);
+  const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % d.nx);
+    const int64_t r = c / d.nx;
+    const int y = (int)(r % d.ny);
+    const int z = (int)(r / d.ny);
+    const int64_t o = (int64_t)z * d.plane + (int64_t)y * d.pitch + x;
+    const int ph = z < solid_height ? (int)phase_map[(int64_t)y * d.nx + x] : LQ;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) base[a * d.fstride + o] = a == ph ? R(1) : R(0);
+    base[4 * d.fstride + o] = (R)mu0;
+    base[5 * d.fstride + o] = (R)mu1;
+  }
+}
+
+// ---------------------------------------------------------- diagnostics
+
+// FP64 partial sums per work group (fixed grid, fixed reduction order, so
+// the result is reproducible run to run).
+template <typename R>
+__global__ __launch_bounds__(256) void diag_partial_kernel(const DevDomain* dom, double t,
+                                                           double* partials) {
+  const DevDomain& d = *dom;
+  const R* base = static_cast<const R*>(d.copy[d.parity]);
+  const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
+  if (t < 0.0) t = (double)d.step * d.dt;
+  double v[kDiagValues] = {0, 0, 0, 0, 0, 0, 0, __builtin_inf(), -__builtin_inf(), 0};
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % d.nx);
+    const int64_t r = c / d.nx;
+    const int y = (int)(r % d.ny);
+    const int z = (int)(r / d.ny);
+    const int64_t o = (int64_t)z * d.plane + (int64_t)y * d.pitch + x;
+    double ph[NP], m[NM], S = 0.0, sum = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      ph[a] = (double)base[a * d.fstride + o];
+      bad |= !__builtin_isfinite(ph[a]);
+      S += ph[a] * ph[a];
+      sum += ph[a];
+      v[2 + a] += ph[a];
+      v[7] = fmin(v[7], ph[a]);
+      v[8] = fmax(v[8], ph[a]);
+    }
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+      m[q] = (double)base[(4 + q) * d.fstride + o];
+      bad |= !__builtin_isfinite(m[q]);
+    }
+    v[6] = fmax(v[6], fabs(sum - 1.0));
+    v[9] += bad ? 1.0 : 0.0;
+    const double T = d.T0 + d.G * ((double)z * d.dx + d.zoff - d.v * t);
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+      double cq = 0.0;
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        const double chi = d.chi0[a][q] + d.chi1[a][q] * (T - d.TE);
+        const double cb = d.c0[a][q] + d.c1[a][q] * (T - d.TE);
+        cq += (ph[a] * ph[a] / S) * (chi * m[q] + cb);
+      }
+      v[q] += cq;
+    }
+  }
+  __shared__ double sh[kDiagValues][256];
+#pragma unroll
+  for (int i = 0; i < kDiagValues; ++i) sh[i][threadIdx.x] = v[i];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int i = 0; i < kDiagValues; ++i) {
+        const double a = sh[i][threadIdx.x], b = sh[i][threadIdx.x + s];
+        sh[i][threadIdx.x] = i == 6 || i == 8 ? fmax(a, b) : (i == 7 ? fmin(a, b) : a + b);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kDiagValues) partials[blockIdx.x * kDiagValues + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, int nblocks,
+                                                        double* out) {
+  const int i = threadIdx.x;
+  if (i >= kDiagValues) return;
+  double acc = i == 7 ? __builtin_inf() : (i == 8 ? -__builtin_inf() : 0.0);
+  for (int b = 0; b < nblocks; ++b) {
+    const double x = partials[b * kDiagValues + i];
+    acc = i == 6 || i == 8 ? fmax(acc, x) : (i == 7 ? fmin(acc, x) : acc + x);
+  }
+  out[i] = acc;
+}
+
+// --------------------------------------------------------------- launches
+
+hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s) {
+  if (prec == 0)
+    prologue_kernel<double><<<L.ndom, 256, 0, s>>>(L.doms, L.ndom);
+  else
+    prologue_kernel<float><<<L.ndom, 256, 0, s>>>(L.doms, L.ndom);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_direct(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
+  const int grid = L.total;
+  if (prec == 0) {
+    if (aniso)
+      phi_direct_kernel<double, true><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    else
+      phi_direct_kernel<double, false><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  } else {
+    if (aniso)
+      phi_direct_kernel<float, true><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    else
+      phi_direct_kernel<float, false><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mu_direct(const LaunchSet& L, int prec, hipStream_t s) {
+  const int grid = L.total;
+  if (prec == 0)
+    mu_direct_kernel<double><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  else
+    mu_direct_kernel<float><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi(const LaunchSet& L, int prec, bool aniso, int variant, hipStream_t s) {
+  if (variant == 1) return launch_phi_tiled(L, prec, aniso, s);
+  return launch_phi_direct(L, prec, aniso, s);
+}
+
+hipError_t launch_mu(const LaunchSet& L, int prec, int variant, hipStream_t s) {
+  if (variant == 1) return launch_mu_tiled(L, prec, s);
+  return launch_mu_direct(L, prec, s);
+}
+
+hipError_t launch_fill(const DevDomain* dom, int prec, int nx, int ny, int nz,
+                       const int8_t* phase_map, int32_t solid_height, double mu0, double mu1,
+                       hipStream_t s) {
+  const int64_t cells = (int64_t)nx * ny * nz;
+  int64_t blocks = (cells + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (prec == 0)
+    fill_kernel<double><<<(int)blocks, 256, 0, s>>>(dom, phase_map, solid_height, mu0, mu1);
+  else
+    fill_kernel<float><<<(int)blocks, 256, 0, s>>>(dom, phase_map, solid_height, mu0, mu1);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const DevDomain* dom, int prec, int nx, int ny, int nz, double t,
+                       double* partials, double* out, hipStream_t s) {
+  (void)nx;
+  (void)ny;
+  (void)nz;
+  if (prec == 0)
+    diag_partial_kernel<double><<<kDiagBlocks, 256, 0, s>>>(dom, t, partials);
+  else
+    diag_partial_kernel<float><<<kDiagBlocks, 256, 0, s>>>(dom, t, partials);
+  diag_final_kernel<<<1, 64, 0, s>>>(partials, kDiagBlocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -1,0 +1,79 @@
+// pf_kernels_common.h -- indexing helpers shared by the sweep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_device.h"
+
+namespace pfk {
+
+// Grid geometry with the boundary rules of the model: periodic in x and y,
+// zero-gradient mirror of one ghost layer in z (Sec. 2.1 boundary handling,
+// applied here by index arithmetic instead of ghost cells).
+struct Geo {
+  int nx, ny, nz, pitch;
+  int64_t plane;
+  __device__ __forceinline__ int xp(int x) const { return x + 1 == nx ? 0 : x + 1; }
+  __device__ __forceinline__ int xm(int x) const { return x == 0 ? nx - 1 : x - 1; }
+  __device__ __forceinline__ int yp(int y) const { return y + 1 == ny ? 0 : y + 1; }
+  __device__ __forceinline__ int ym(int y) const { return y == 0 ? ny - 1 : y - 1; }
+  __device__ __forceinline__ int zp(int z) const { return z + 1 >= nz ? nz - 1 : z + 1; }
+  __device__ __forceinline__ int zm(int z) const { return z <= 0 ? 0 : z - 1; }
+  __device__ __forceinline__ int64_t at(int x, int y, int z) const {
+    return (int64_t)z * plane + (int64_t)y * pitch + x;
+  }
+};
+
+__device__ __forceinline__ Geo make_geo(const DevDomain& d) {
+  Geo g;
+  g.nx = d.nx;
+  g.ny = d.ny;
+  g.nz = d.nz;
+  g.pitch = d.pitch;
+  g.plane = d.plane;
+  return g;
+}
+
+// Domain owning flattened work item `item` (binary search of the prefix sums).
+__device__ __forceinline__ int find_domain(const int32_t* first, int ndom, int item) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One work item: an x-y tile of tx * ty columns and a chunk of zc planes.
+struct WorkTile {
+  int x0, y0;  // tile origin
+  int lx, ly;  // this thread's column inside the tile
+  int x, y;    // this thread's column in the domain
+  int z0, z1;  // planes [z0, z1)
+  bool valid;  // column inside the domain
+};
+
+__device__ __forceinline__ WorkTile decode_item(const DevDomain& d, int local, int tid) {
+  WorkTile w;
+  const int ix = local % d.ntx;
+  const int r = local / d.ntx;
+  const int iy = r % d.nty;
+  const int iz = r / d.nty;
+  w.lx = tid % d.tx;
+  w.ly = tid / d.tx;
+  w.x0 = ix * d.tx;
+  w.y0 = iy * d.ty;
+  w.x = w.x0 + w.lx;
+  w.y = w.y0 + w.ly;
+  w.z0 = iz * d.zc;
+  w.z1 = min(d.nz, w.z0 + d.zc);
+  w.valid = w.x < d.nx && w.y < d.ny;
+  return w;
+}
+
+hipError_t launch_phi_tiled(const struct LaunchSet& L, int prec, bool aniso, hipStream_t s);
+hipError_t launch_mu_tiled(const struct LaunchSet& L, int prec, hipStream_t s);
+
+}  // namespace pfk

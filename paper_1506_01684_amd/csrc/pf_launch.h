@@ -1,0 +1,44 @@
+// pf_launch.h -- host-side launch wrappers of the phase-field kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_device.h"
+
+namespace pfk {
+
+// A launch covers `ndom` domains whose descriptors live in device memory at
+// `doms`; `first` (device, ndom+1 entries) is the prefix sum of work items
+// (x-y tiles times z chunks) per domain, `total` its last entry.
+struct LaunchSet {
+  DevDomain* const* doms;  // device array of descriptor pointers
+  const int32_t* first;
+  int32_t ndom;
+  int32_t total;
+  int32_t max_nz;  // largest nz among the domains (prologue loop bound)
+};
+
+// Threads per work group of the sweeps (tile tx * ty).
+constexpr int kTileThreads = 256;
+
+hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s);
+hipError_t launch_phi(const LaunchSet& L, int prec, bool aniso, int variant, hipStream_t s);
+hipError_t launch_mu(const LaunchSet& L, int prec, int variant, hipStream_t s);
+
+// Fill the current state copy: column phase map (int8, nx*ny) below
+// solid_height, liquid above, uniform mu.
+hipError_t launch_fill(const DevDomain* dom, int prec, int nx, int ny, int nz,
+                       const int8_t* phase_map, int32_t solid_height, double mu0, double mu1,
+                       hipStream_t s);
+
+// Diagnostics of the state in copy `parity` at time t (t < 0: the time
+// of the device step counter): out[0..9] =
+// sum_c0, sum_c1, sum_phi0..3, max |sum phi - 1|, min phi, max phi,
+// non-finite cell count.  `partials` holds kDiagBlocks * 10 doubles.
+constexpr int kDiagBlocks = 480;
+constexpr int kDiagValues = 10;
+hipError_t launch_diag(const DevDomain* dom, int prec, int nx, int ny, int nz, double t,
+                       double* partials, double* out, hipStream_t s);
+
+}  // namespace pfk

@@ -1,0 +1,814 @@
+// pf_runtime.hip -- host runtime behind the C ABI declared in pfsolve.h.
+//
+// Owns the device layout of a domain (one allocation: descriptor, work-item
+// table, per-plane coefficient table, diagnostics scratch, Voronoi phase map,
+// and two copies of the six fields phi_0..3, mu_0..1, structure of arrays,
+// x fastest, rows padded to 128 bytes), validates parameters, resolves the
+// time step, and enqueues the kernels of Algorithm 1 on the domain's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pfsolve.h"
+#include "pf_device.h"
+#include "pf_launch.h"
+
+using namespace pfk;
+
+namespace {
+
+thread_local std::string g_last_error;
+std::atomic<int> g_variant{1};
+
+pf_status fail(pf_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define PF_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PF_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  int32_t pitch;
+  int64_t plane, fstride;  // elements
+  size_t elem;
+  size_t off_desc, off_ptrs, off_first, off_coef, off_partials, off_diag, off_map, off_fields;
+  size_t copy_bytes, total;
+};
+
+bool make_layout(const pf_domain_desc& d, Layout& L) {
+  if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return false;
+  if (d.prec != PF_FP64 && d.prec != PF_FP32) return false;
+  if (!(d.dx > 0.0) || !std::isfinite(d.dx)) return false;
+  L.elem = d.prec == PF_FP64 ? 8 : 4;
+  const int64_t row_elems = 128 / (int64_t)L.elem;
+  const int64_t pitch = (d.nx + row_elems - 1) / row_elems * row_elems;
+  if (pitch > INT32_MAX) return false;
+  L.pitch = (int32_t)pitch;
+  const long double cells = (long double)pitch * d.ny * d.nz;
+  if (cells * L.elem * 12 > (long double)(1ull << 62)) return false;
+  L.plane = pitch * (int64_t)d.ny;
+  // fields start 4 KiB apart plus a 2 KiB skew, so that equal offsets in
+  // different fields do not fall on the same memory channel
+  const int64_t fe = L.plane * (int64_t)d.nz;
+  const int64_t a4k = 4096 / (int64_t)L.elem, skew = 2048 / (int64_t)L.elem;
+  L.fstride = (fe + a4k - 1) / a4k * a4k + skew;
+  size_t off = 0;
+  L.off_desc = off;
+  off = align_up(off + sizeof(DevDomain), kAlign);
+  L.off_ptrs = off;
+  off = align_up(off + sizeof(void*), kAlign);
+  L.off_first = off;
+  off = align_up(off + 2 * sizeof(int32_t), kAlign);
+  L.off_coef = off;
+  const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
+  off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
+  L.off_partials = off;
+  off = align_up(off + sizeof(double) * kDiagBlocks * kDiagValues, kAlign);
+  L.off_diag = off;
+  off = align_up(off + sizeof(double) * kDiagValues, kAlign);
+  L.off_map = off;
+  off = align_up(off + (size_t)d.nx * (size_t)d.ny, 4096);
+  L.off_fields = off;
+  L.copy_bytes = align_up((size_t)L.fstride * NFIELD * L.elem, 4096);
+  L.total = off + 2 * L.copy_bytes;
+  return true;
+}
+
+struct Tiling {
+  int32_t tx, ty, zc, ntx, nty, nzc;
+};
+
+Tiling choose_tiling(int nx, int ny, int nz) {
+  Tiling t;
+  t.tx = nx >= 48 ? 64 : 32;
+  t.ty = kTileThreads / t.tx;
+  t.ntx = (nx + t.tx - 1) / t.tx;
+  t.nty = (ny + t.ty - 1) / t.ty;
+  const int64_t tiles = (int64_t)t.ntx * t.nty;
+  int64_t zc = ((int64_t)nz * tiles + 4095) / 4096;
+  zc = std::max<int64_t>(8, std::min<int64_t>(256, zc));
+  t.zc = (int32_t)std::min<int64_t>(zc, nz);
+  t.nzc = (nz + t.zc - 1) / t.zc;
+  return t;
+}
+
+uint64_t splitmix64_next(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Column -> solid phase map of the Voronoi initial state (2D).
+void voronoi_columns(int nx, int ny, uint64_t seed, int nseeds, std::vector<int8_t>& map) {
+  map.assign((size_t)nx * ny, (int8_t)LQ);
+  if (nseeds <= 0) return;
+  std::vector<double> sx(nseeds), sy(nseeds);
+  uint64_t st = seed;
+  for (int s = 0; s < nseeds; ++s) {
+    sx[s] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 * nx;
+    sy[s] = (double)(splitmix64_next(st) >> 11) * 0x1.0p-53 * ny;
+  }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double cx = (double)i + 0.5, cy = (double)j + 0.5;
+      double best_d = INFINITY;
+      int best = 0;
+      for (int s = 0; s < nseeds; ++s) {
+        double ax = std::fabs(cx - sx[s]), ay = std::fabs(cy - sy[s]);
+        if (nx - ax < ax) ax = nx - ax;
+        if (ny - ay < ay) ay = ny - ay;
+        const double d2 = ax * ax + ay * ay;
+        if (d2 < best_d) {
+          best_d = d2;
+          best = s;
+        }
+      }
+      map[(size_t)j * nx + i] = (int8_t)(best % 3);
+    }
+}
+
+}  // namespace
+
+struct pf_domain {
+  pf_domain_desc desc;
+  Layout L;
+  Tiling T;
+  char* base = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  DevDomain host;  // host mirror of the descriptor's static part
+  DevDomain* dev = nullptr;
+  DevDomain** dev_ptrs = nullptr;
+  int32_t* dev_first = nullptr;
+  bool params_set = false, fields_set = false, aniso = false;
+  double dt = 0.0, bound = 0.0;
+  int32_t diag_every = 0;
+  int64_t since_diag = 0;
+  bool diag_pending = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  pf_pack* pack = nullptr;
+
+  char* fields(int copy) const { return base + L.off_fields + (size_t)copy * L.copy_bytes; }
+  double* partials() const { return reinterpret_cast<double*>(base + L.off_partials); }
+  double* diag_out() const { return reinterpret_cast<double*>(base + L.off_diag); }
+  LaunchSet launch_set() const {
+    LaunchSet s;
+    s.doms = dev_ptrs;
+    s.first = dev_first;
+    s.ndom = 1;
+    s.total = T.ntx * T.nty * T.nzc;
+    s.max_nz = desc.nz;
+    return s;
+  }
+};
+
+namespace {
+
+pf_status upload_desc(pf_domain* d) {
+  PF_HIP(hipMemcpyAsync(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
+  return PF_OK;
+}
+
+// Read the device descriptor's dynamic state (step, parity, steps left).
+pf_status fetch_state(pf_domain* d, DevDomain& out) {
+  PF_HIP(hipMemcpyAsync(&out, d->dev, sizeof(DevDomain), hipMemcpyDeviceToHost, d->stream));
+  PF_HIP(hipStreamSynchronize(d->stream));
+  return PF_OK;
+}
+
+double temperature(const pf_params& p, double z, double t) {
+  return p.T0 + p.G * (z + p.zoff - p.v * t);
+}
+
+pf_status validate_and_bound(const pf_domain* d, const pf_params& p, double& bound) {
+  const double dx = d->desc.dx;
+  if (!(p.eps > 0.0) || !std::isfinite(p.eps)) return fail(PF_ERR_INVALID_ARG, "eps must be > 0");
+  double tau_min = INFINITY, gmax = 0.0, dmax = 0.0;
+  for (int a = 0; a < NP; ++a) {
+    if (!(p.tau[a] > 0.0)) return fail(PF_ERR_INVALID_ARG, "tau must be > 0");
+    if (!(p.D[a] >= 0.0)) return fail(PF_ERR_INVALID_ARG, "D must be >= 0");
+    tau_min = std::min(tau_min, p.tau[a]);
+    for (int b = 0; b < NP; ++b) {
+      if (a == b) continue;
+      if (!(p.gamma[a][b] >= 0.0) || p.gamma[a][b] != p.gamma[b][a])
+        return fail(PF_ERR_INVALID_ARG, "gamma must be symmetric and >= 0");
+      if (!(p.aniso_delta[a][b] >= 0.0) || !(p.aniso_delta[a][b] < 1.0 / 15.0) ||
+          p.aniso_delta[a][b] != p.aniso_delta[b][a])
+        return fail(PF_ERR_INVALID_ARG, "anisotropy delta must be symmetric and in [0, 1/15)");
+      gmax = std::max(gmax, p.gamma[a][b]);
+      dmax = std::max(dmax, p.aniso_delta[a][b]);
+    }
+  }
+  if (!(p.gamma3 >= 0.0)) return fail(PF_ERR_INVALID_ARG, "gamma3 must be >= 0");
+  const double Tb = temperature(p, 0.0, 0.0);
+  const double Tt = temperature(p, (double)(d->desc.nz - 1) * dx, 0.0);
+  const double Tmax = std::max(Tb, Tt), Tmin = std::min(Tb, Tt);
+  if (!(Tmin > 0.0)) return fail(PF_ERR_INVALID_ARG, "temperature must be > 0 over the domain");
+  double chi_min = INFINITY, dchi_max = 0.0;
+  for (int a = 0; a < NP; ++a)
+    for (int q = 0; q < NM; ++q)
+      for (double T : {Tmin, Tmax}) {
+        const double c = p.chi0[a][q] + p.chi1[a][q] * (T - p.TE);
+        if (!(c > 0.0)) return fail(PF_ERR_INVALID_ARG, "susceptibility must be > 0");
+        chi_min = std::min(chi_min, c);
+        dchi_max = std::max(dchi_max, p.D[a] * c);
+      }
+  // phase field: two-phase diffusivity 2 gamma T / tau, 7-point limit
+  // dx^2/(6 D), cubic stiffening (1+delta)(1+15 delta)
+  const double kappa = (1.0 + dmax) * (1.0 + 15.0 * dmax);
+  const double dt_phi = gmax > 0.0 ? dx * dx * tau_min / (12.0 * gmax * Tmax * kappa) : INFINITY;
+  const double dt_mu = dchi_max > 0.0 ? dx * dx * chi_min / (6.0 * dchi_max) : INFINITY;
+  bound = std::min(dt_phi, dt_mu);
+  if (!std::isfinite(bound)) return fail(PF_ERR_INVALID_ARG, "no finite stability bound");
+  return PF_OK;
+}
+
+template <typename R>
+void fill_kparams(KParams<R>& k, const pf_params& p, double dt, double dx, bool aniso) {
+  const double pi = 3.14159265358979323846;
+  for (int a = 0; a < NP; ++a)
+    for (int b = a + 1; b < NP; ++b) {
+      const int i = pair_index(a, b);
+      k.g1[i] = (R)p.gamma[a][b];
+      k.g2[i] = (R)(2.0 * p.gamma[a][b]);
+      k.g16[i] = (R)(16.0 / (pi * pi) * p.gamma[a][b]);
+      k.delta[i] = (R)p.aniso_delta[a][b];
+    }
+  k.gamma3 = (R)p.gamma3;
+  for (int a = 0; a < NP; ++a) k.rate[a] = (R)(dt / (p.tau[a] * p.eps));
+  k.inv_dx = (R)(1.0 / dx);
+  k.inv_4dx = (R)(1.0 / (4.0 * dx));
+  k.dt = (R)dt;
+  k.half_inv_dt = (R)(0.5 / dt);
+  k.pieps4 = (R)(pi * p.eps / 4.0);
+  k.aniso = aniso ? 1 : 0;
+  k.antitrap = p.antitrapping ? 1 : 0;
+  k.mu_frozen = p.mu_frozen ? 1 : 0;
+  k.pad = 0;
+}
+
+pf_status enqueue_step(pf_domain* d, hipEvent_t* ev) {
+  const LaunchSet s = d->launch_set();
+  const int prec = d->desc.prec;
+  const int var = g_variant.load();
+  PF_HIP(launch_prologue(s, prec, d->stream));
+  if (ev) PF_HIP(hipEventRecord(ev[0], d->stream));
+  PF_HIP(launch_phi(s, prec, d->aniso, var, d->stream));
+  if (ev) PF_HIP(hipEventRecord(ev[1], d->stream));
+  PF_HIP(launch_mu(s, prec, var, d->stream));
+  if (ev) PF_HIP(hipEventRecord(ev[2], d->stream));
+  return PF_OK;
+}
+
+pf_status check_state(const pf_domain* d) {
+  if (!d) return fail(PF_ERR_INVALID_ARG, "null domain");
+  if (!d->params_set) return fail(PF_ERR_STATE, "pf_set_params has not been called");
+  if (!d->fields_set) return fail(PF_ERR_STATE, "pf_init_fields has not been called");
+  return PF_OK;
+}
+
+pf_status run_diag(pf_domain* d, double t, double out[kDiagValues]) {
+  PF_HIP(launch_diag(d->dev, d->desc.prec, d->desc.nx, d->desc.ny, d->desc.nz, t, d->partials(),
+                     d->diag_out(), d->stream));
+  PF_HIP(hipMemcpyAsync(out, d->diag_out(), sizeof(double) * kDiagValues, hipMemcpyDeviceToHost,
+                        d->stream));
+  PF_HIP(hipStreamSynchronize(d->stream));
+  return PF_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* pf_last_error(void) { return g_last_error.c_str(); }
+
+pf_status pf_set_variant(int32_t variant) {
+  if (variant != 0 && variant != 1) return fail(PF_ERR_INVALID_ARG, "variant must be 0 or 1");
+  g_variant.store(variant);
+  return PF_OK;
+}
+
+pf_status pf_required_bytes(const pf_domain_desc* desc, size_t* out) {
+  if (!desc || !out) return fail(PF_ERR_INVALID_ARG, "null argument");
+  Layout L;
+  if (!make_layout(*desc, L)) return fail(PF_ERR_INVALID_ARG, "invalid domain description");
+  *out = L.total;
+  return PF_OK;
+}
+
+pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* borrowed,
+                           void* stream, pf_domain** out) {
+  if (!desc || !out) return fail(PF_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  Layout L;
+  if (!make_layout(*desc, L)) return fail(PF_ERR_INVALID_ARG, "invalid domain description");
+  pf_domain* d = new (std::nothrow) pf_domain();
+  if (!d) return fail(PF_ERR_OOM, "host allocation failed");
+  d->desc = *desc;
+  d->L = L;
+  d->T = choose_tiling(desc->nx, desc->ny, desc->nz);
+  d->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&d->device) != hipSuccess) {
+    delete d;
+    return fail(PF_ERR_DEVICE, "hipGetDevice failed");
+  }
+  if (borrowed) {
+    if (!borrowed->base || borrowed->bytes < L.total ||
+        reinterpret_cast<uintptr_t>(borrowed->base) % kAlign != 0) {
+      delete d;
+      return fail(PF_ERR_INVALID_ARG, "borrowed buffer too small or misaligned");
+    }
+    d->base = static_cast<char*>(borrowed->base);
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, L.total) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      delete d;
+      return fail(PF_ERR_OOM, "hipMalloc of " + std::to_string(L.total) + " bytes failed");
+    }
+    d->base = static_cast<char*>(p);
+    d->owned = true;
+  }
+  d->dev = reinterpret_cast<DevDomain*>(d->base + L.off_desc);
+  d->dev_ptrs = reinterpret_cast<DevDomain**>(d->base + L.off_ptrs);
+  d->dev_first = reinterpret_cast<int32_t*>(d->base + L.off_first);
+  DevDomain& h = d->host;
+  std::memset(&h, 0, sizeof(h));
+  h.nx = desc->nx;
+  h.ny = desc->ny;
+  h.nz = desc->nz;
+  h.pitch = L.pitch;
+  h.plane = L.plane;
+  h.fstride = L.fstride;
+  h.tx = d->T.tx;
+  h.ty = d->T.ty;
+  h.zc = d->T.zc;
+  h.ntx = d->T.ntx;
+  h.nty = d->T.nty;
+  h.nzc = d->T.nzc;
+  h.prec = desc->prec;
+  h.steps_left = -1;
+  h.copy[0] = d->fields(0);
+  h.copy[1] = d->fields(1);
+  h.coef = d->base + L.off_coef;
+  h.dx = desc->dx;
+  int32_t first[2] = {0, d->T.ntx * d->T.nty * d->T.nzc};
+  DevDomain* self = d->dev;
+  pf_status st = PF_OK;
+  if (hipMemcpyAsync(d->dev_ptrs, &self, sizeof(self), hipMemcpyHostToDevice, d->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(d->dev_first, first, sizeof(first), hipMemcpyHostToDevice, d->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(d->stream) != hipSuccess)
+    st = fail(PF_ERR_DEVICE, "descriptor upload failed");
+  if (st == PF_OK) st = upload_desc(d);
+  for (int i = 0; st == PF_OK && i < 4; ++i)
+    if (hipEventCreate(&d->ev[i]) != hipSuccess) st = fail(PF_ERR_DEVICE, "hipEventCreate failed");
+  if (st == PF_OK && hipStreamSynchronize(d->stream) != hipSuccess)
+    st = fail(PF_ERR_DEVICE, "stream synchronisation failed");
+  if (st != PF_OK) {
+    pf_destroy(d);
+    return st;
+  }
+  *out = d;
+  return PF_OK;
+}
+
+pf_status pf_set_params(pf_domain* d, const pf_params* p) {
+  if (!d || !p) return fail(PF_ERR_INVALID_ARG, "null argument");
+  if (p->diag_every < 0) return fail(PF_ERR_INVALID_ARG, "diag_every must be >= 0");
+  double bound = 0.0;
+  pf_status st = validate_and_bound(d, *p, bound);
+  if (st != PF_OK) return st;
+  double dt = p->dt;
+  if (!(dt > 0.0)) dt = 0.25 * bound;
+  else if (dt > bound)
+    return fail(PF_ERR_UNSTABLE, "dt " + std::to_string(dt) + " above the stability bound " +
+                                     std::to_string(bound));
+  bool aniso = false;
+  for (int a = 0; a < NP; ++a)
+    for (int b = a + 1; b < NP; ++b) aniso |= p->aniso_delta[a][b] > 0.0;
+  DevDomain& h = d->host;
+  h.dt = dt;
+  h.eps = p->eps;
+  h.TE = p->TE;
+  h.T0 = p->T0;
+  h.G = p->G;
+  h.v = p->v;
+  h.zoff = p->zoff;
+  std::memcpy(h.chi0, p->chi0, sizeof(h.chi0));
+  std::memcpy(h.chi1, p->chi1, sizeof(h.chi1));
+  std::memcpy(h.c0, p->c0, sizeof(h.c0));
+  std::memcpy(h.c1, p->c1, sizeof(h.c1));
+  std::memcpy(h.w0, p->w0, sizeof(h.w0));
+  std::memcpy(h.w1, p->w1, sizeof(h.w1));
+  std::memcpy(h.D, p->D, sizeof(h.D));
+  fill_kparams(h.kp64, *p, dt, d->desc.dx, aniso);
+  fill_kparams(h.kp32, *p, dt, d->desc.dx, aniso);
+  // keep the device's dynamic state (step, parity) when parameters change
+  if (d->fields_set) {
+    DevDomain cur;
+    if ((st = fetch_state(d, cur)) != PF_OK) return st;
+    h.step = cur.step;
+    h.parity = cur.parity;
+  }
+  h.steps_left = -1;
+  if ((st = upload_desc(d)) != PF_OK) return st;
+  PF_HIP(hipStreamSynchronize(d->stream));
+  d->dt = dt;
+  d->bound = bound;
+  d->aniso = aniso;
+  d->diag_every = p->diag_every;
+  d->params_set = true;
+  return PF_OK;
+}
+
+pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound) {
+  if (!d) return fail(PF_ERR_INVALID_ARG, "null domain");
+  if (!d->params_set) return fail(PF_ERR_STATE, "pf_set_params has not been called");
+  if (dt) *dt = d->dt;
+  if (bound) *bound = d->bound;
+  return PF_OK;
+}
+
+pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
+  if (!d || !in) return fail(PF_ERR_INVALID_ARG, "null argument");
+  const pf_domain_desc& g = d->desc;
+  const Layout& L = d->L;
+  pf_status st;
+  // the state lives in copy 0 from now on
+  DevDomain& h = d->host;
+  if (d->params_set) {
+    DevDomain cur;
+    if ((st = fetch_state(d, cur)) != PF_OK) return st;
+  }
+  h.step = 0;
+  h.parity = 0;
+  h.steps_left = -1;
+  if ((st = upload_desc(d)) != PF_OK) return st;
+  if (in->kind == PF_INIT_VORONOI) {
+    if (in->nseeds < 0 || in->solid_height < 0)
+      return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
+    std::vector<int8_t> map;
+    voronoi_columns(g.nx, g.ny, in->seed, in->nseeds, map);
+    int8_t* dmap = reinterpret_cast<int8_t*>(d->base + L.off_map);
+    PF_HIP(hipMemcpyAsync(dmap, map.data(), map.size(), hipMemcpyHostToDevice, d->stream));
+    PF_HIP(launch_fill(d->dev, g.prec, g.nx, g.ny, g.nz, dmap, in->solid_height, in->mu_init[0],
+                       in->mu_init[1], d->stream));
+    PF_HIP(hipStreamSynchronize(d->stream));
+  } else if (in->kind == PF_INIT_HOST) {
+    if (!in->phi || !in->mu) return fail(PF_ERR_INVALID_ARG, "HOST init needs phi and mu");
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    std::vector<char> buf(L.copy_bytes, 0);
+    for (int f = 0; f < NFIELD; ++f) {
+      const double* srcf = f < NP ? in->phi + (size_t)f * n : in->mu + (size_t)(f - NP) * n;
+      for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+          const double* row = srcf + ((size_t)z * g.ny + y) * g.nx;
+          const size_t o = (size_t)f * L.fstride + (size_t)z * L.plane + (size_t)y * L.pitch;
+          if (g.prec == PF_FP64) {
+            std::memcpy(buf.data() + o * 8, row, sizeof(double) * g.nx);
+          } else {
+            float* dstp = reinterpret_cast<float*>(buf.data()) + o;
+            for (int x = 0; x < g.nx; ++x) dstp[x] = (float)row[x];
+          }
+        }
+    }
+    PF_HIP(hipMemcpyAsync(d->fields(0), buf.data(), L.copy_bytes, hipMemcpyHostToDevice,
+                          d->stream));
+    PF_HIP(hipStreamSynchronize(d->stream));
+  } else {
+    return fail(PF_ERR_INVALID_ARG, "unknown init kind");
+  }
+  d->fields_set = true;
+  d->since_diag = 0;
+  d->diag_pending = false;
+  return PF_OK;
+}
+
+pf_status pf_set_time(pf_domain* d, int64_t step) {
+  pf_status st = check_state(d);
+  if (st != PF_OK) return st;
+  if (step < 0) return fail(PF_ERR_INVALID_ARG, "step must be >= 0");
+  DevDomain cur;
+  if ((st = fetch_state(d, cur)) != PF_OK) return st;
+  d->host.step = step;
+  d->host.parity = cur.parity;
+  d->host.steps_left = -1;
+  if ((st = upload_desc(d)) != PF_OK) return st;
+  PF_HIP(hipStreamSynchronize(d->stream));
+  return PF_OK;
+}
+
+pf_status pf_step(pf_domain* d, int64_t n) {
+  pf_status st = check_state(d);
+  if (st != PF_OK) return st;
+  if (n < 0) return fail(PF_ERR_INVALID_ARG, "n must be >= 0");
+  if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
+  for (int64_t i = 0; i < n; ++i) {
+    if ((st = enqueue_step(d, nullptr)) != PF_OK) return st;
+    if (d->diag_every > 0 && ++d->since_diag >= d->diag_every) {
+      d->since_diag = 0;
+      PF_HIP(launch_diag(d->dev, d->desc.prec, d->desc.nx, d->desc.ny, d->desc.nz, -1.0,
+                         d->partials(), d->diag_out(), d->stream));
+      d->diag_pending = true;
+    }
+  }
+  return PF_OK;
+}
+
+pf_status pf_step_timed(pf_domain* d, int64_t n, double* phi_ms, double* mu_ms) {
+  pf_status st = check_state(d);
+  if (st != PF_OK) return st;
+  if (n < 0) return fail(PF_ERR_INVALID_ARG, "n must be >= 0");
+  if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
+  double tp = 0.0, tm = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if ((st = enqueue_step(d, d->ev)) != PF_OK) return st;
+    PF_HIP(hipEventSynchronize(d->ev[2]));
+    float a = 0.f, b = 0.f;
+    PF_HIP(hipEventElapsedTime(&a, d->ev[0], d->ev[1]));
+    PF_HIP(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
+    tp += a;
+    tm += b;
+  }
+  if (phi_ms) *phi_ms += tp;
+  if (mu_ms) *mu_ms += tm;
+  return PF_OK;
+}
+
+pf_status pf_sync(pf_domain* d) {
+  if (!d) return fail(PF_ERR_INVALID_ARG, "null domain");
+  PF_HIP(hipStreamSynchronize(d->stream));
+  if (d->diag_pending) {
+    double v[kDiagValues];
+    PF_HIP(hipMemcpy(v, d->diag_out(), sizeof(v), hipMemcpyDeviceToHost));
+    d->diag_pending = false;
+    if (v[9] > 0.0)
+      return fail(PF_ERR_NONFINITE, "diagnostics found " + std::to_string((int64_t)v[9]) +
+                                        " non-finite cells");
+  }
+  return PF_OK;
+}
+
+pf_status pf_get_step(const pf_domain* d, int64_t* step) {
+  if (!d || !step) return fail(PF_ERR_INVALID_ARG, "null argument");
+  DevDomain cur;
+  pf_status st = fetch_state(const_cast<pf_domain*>(d), cur);
+  if (st != PF_OK) return st;
+  *step = cur.step;
+  return PF_OK;
+}
+
+pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
+  pf_status st = check_state(d);
+  if (st != PF_OK) return st;
+  PF_HIP(hipStreamSynchronize(d->stream));
+  DevDomain cur;
+  if ((st = fetch_state(d, cur)) != PF_OK) return st;
+  const pf_domain_desc& g = d->desc;
+  const Layout& L = d->L;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  if (phi || mu) {
+    std::vector<char> buf(L.copy_bytes);
+    PF_HIP(hipMemcpy(buf.data(), d->fields(cur.parity), L.copy_bytes, hipMemcpyDeviceToHost));
+    for (int f = 0; f < NFIELD; ++f) {
+      double* dstf = f < NP ? (phi ? phi + (size_t)f * n : nullptr)
+                            : (mu ? mu + (size_t)(f - NP) * n : nullptr);
+      if (!dstf) continue;
+      for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+          double* row = dstf + ((size_t)z * g.ny + y) * g.nx;
+          const size_t o = (size_t)f * L.fstride + (size_t)z * L.plane + (size_t)y * L.pitch;
+          if (g.prec == PF_FP64) {
+            std::memcpy(row, buf.data() + o * 8, sizeof(double) * g.nx);
+          } else {
+            const float* s = reinterpret_cast<const float*>(buf.data()) + o;
+            for (int x = 0; x < g.nx; ++x) row[x] = (double)s[x];
+          }
+        }
+    }
+  }
+  if (diag) {
+    const double t = (double)cur.step * d->dt;
+    double v[kDiagValues];
+    if ((st = run_diag(d, t, v)) != PF_OK) return st;
+    diag->t = t;
+    diag->step = cur.step;
+    diag->sum_c[0] = v[0];
+    diag->sum_c[1] = v[1];
+    for (int a = 0; a < NP; ++a) diag->sum_phi[a] = v[2 + a];
+    diag->max_simplex_dev = v[6];
+    diag->phi_min = v[7];
+    diag->phi_max = v[8];
+    diag->nonfinite = (int64_t)v[9];
+    if (diag->nonfinite > 0)
+      return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
+  }
+  return PF_OK;
+}
+
+void pf_destroy(pf_domain* d) {
+  if (!d) return;
+  (void)hipStreamSynchronize(d->stream);
+  for (auto& e : d->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (d->owned && d->base) (void)hipFree(d->base);
+  delete d;
+}
+
+}  // extern "C"
+
+// ==================================================================== packs
+
+struct pf_pack {
+  int32_t prec;
+  hipStream_t stream;
+  int32_t max_domains;
+  std::vector<pf_domain*> members;
+  DevDomain** dev_ptrs = nullptr;
+  int32_t* dev_first = nullptr;
+  int32_t total = 0, max_nz = 0;
+  bool any_aniso = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;
+};
+
+namespace {
+
+void drop_graph(pf_pack* pk) {
+  if (pk->exec) (void)hipGraphExecDestroy(pk->exec);
+  if (pk->graph) (void)hipGraphDestroy(pk->graph);
+  pk->exec = nullptr;
+  pk->graph = nullptr;
+}
+
+pf_status rebuild_pack(pf_pack* pk) {
+  std::vector<DevDomain*> ptrs;
+  std::vector<int32_t> first(1, 0);
+  pk->any_aniso = false;
+  pk->max_nz = 0;
+  for (pf_domain* d : pk->members) {
+    ptrs.push_back(d->dev);
+    first.push_back(first.back() + d->T.ntx * d->T.nty * d->T.nzc);
+    pk->any_aniso |= d->aniso;
+    pk->max_nz = std::max(pk->max_nz, d->desc.nz);
+  }
+  pk->total = first.back();
+  if (!ptrs.empty()) {
+    PF_HIP(hipMemcpyAsync(pk->dev_ptrs, ptrs.data(), sizeof(DevDomain*) * ptrs.size(),
+                          hipMemcpyHostToDevice, pk->stream));
+    PF_HIP(hipMemcpyAsync(pk->dev_first, first.data(), sizeof(int32_t) * first.size(),
+                          hipMemcpyHostToDevice, pk->stream));
+    PF_HIP(hipStreamSynchronize(pk->stream));
+  }
+  drop_graph(pk);
+  if (!ptrs.empty()) {
+    LaunchSet s;
+    s.doms = pk->dev_ptrs;
+    s.first = pk->dev_first;
+    s.ndom = (int32_t)ptrs.size();
+    s.total = pk->total;
+    s.max_nz = pk->max_nz;
+    const int var = g_variant.load();
+    PF_HIP(hipStreamBeginCapture(pk->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = launch_prologue(s, pk->prec, pk->stream);
+    hipError_t e2 = launch_phi(s, pk->prec, pk->any_aniso, var, pk->stream);
+    hipError_t e3 = launch_mu(s, pk->prec, var, pk->stream);
+    hipError_t e4 = hipStreamEndCapture(pk->stream, &pk->graph);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
+      return fail(PF_ERR_DEVICE, "pack step capture failed");
+    PF_HIP(hipGraphInstantiate(&pk->exec, pk->graph, nullptr, nullptr, 0));
+  }
+  pk->dirty = false;
+  return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_pack_create(int32_t prec, void* stream, int32_t max_domains, pf_pack** out) {
+  if (!out) return fail(PF_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (prec != PF_FP64 && prec != PF_FP32) return fail(PF_ERR_INVALID_ARG, "bad precision");
+  if (max_domains <= 0 || max_domains > 4096) return fail(PF_ERR_INVALID_ARG, "bad max_domains");
+  pf_pack* pk = new (std::nothrow) pf_pack();
+  if (!pk) return fail(PF_ERR_OOM, "host allocation failed");
+  pk->prec = prec;
+  pk->stream = static_cast<hipStream_t>(stream);
+  pk->max_domains = max_domains;
+  void* p = nullptr;
+  const size_t bytes = align_up(sizeof(DevDomain*) * max_domains, kAlign) +
+                       sizeof(int32_t) * (max_domains + 1);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete pk;
+    return fail(PF_ERR_OOM, "pack table allocation failed");
+  }
+  pk->dev_ptrs = static_cast<DevDomain**>(p);
+  pk->dev_first = reinterpret_cast<int32_t*>(static_cast<char*>(p) +
+                                             align_up(sizeof(DevDomain*) * max_domains, kAlign));
+  *out = pk;
+  return PF_OK;
+}
+
+pf_status pf_pack_add(pf_pack* pk, pf_domain* d, int64_t nsteps) {
+  if (!pk || !d) return fail(PF_ERR_INVALID_ARG, "null argument");
+  pf_status st = check_state(d);
+  if (st != PF_OK) return st;
+  if (d->pack) return fail(PF_ERR_STATE, "domain already in a pack");
+  if (d->desc.prec != pk->prec) return fail(PF_ERR_INVALID_ARG, "precision mismatch");
+  if ((int32_t)pk->members.size() >= pk->max_domains) return fail(PF_ERR_STATE, "pack is full");
+  if (nsteps < 0) return fail(PF_ERR_INVALID_ARG, "nsteps must be >= 0");
+  PF_HIP(hipStreamSynchronize(d->stream));
+  PF_HIP(hipStreamSynchronize(pk->stream));
+  PF_HIP(hipMemcpy(reinterpret_cast<char*>(d->dev) + offsetof(DevDomain, steps_left), &nsteps,
+                   sizeof(nsteps), hipMemcpyHostToDevice));
+  pk->members.push_back(d);
+  d->pack = pk;
+  pk->dirty = true;
+  return PF_OK;
+}
+
+pf_status pf_pack_remove(pf_pack* pk, pf_domain* d) {
+  if (!pk || !d) return fail(PF_ERR_INVALID_ARG, "null argument");
+  auto it = std::find(pk->members.begin(), pk->members.end(), d);
+  if (it == pk->members.end()) return fail(PF_ERR_INVALID_ARG, "not a member");
+  PF_HIP(hipStreamSynchronize(pk->stream));
+  int64_t unlimited = -1;
+  PF_HIP(hipMemcpy(reinterpret_cast<char*>(d->dev) + offsetof(DevDomain, steps_left), &unlimited,
+                   sizeof(unlimited), hipMemcpyHostToDevice));
+  pk->members.erase(it);
+  d->pack = nullptr;
+  pk->dirty = true;
+  return PF_OK;
+}
+
+pf_status pf_pack_remaining(pf_pack* pk, const pf_domain* d, int64_t* left) {
+  if (!pk || !d || !left) return fail(PF_ERR_INVALID_ARG, "null argument");
+  PF_HIP(hipStreamSynchronize(pk->stream));
+  PF_HIP(hipMemcpy(left, reinterpret_cast<const char*>(d->dev) + offsetof(DevDomain, steps_left),
+                   sizeof(int64_t), hipMemcpyDeviceToHost));
+  return PF_OK;
+}
+
+pf_status pf_pack_step(pf_pack* pk, int64_t rounds, int32_t* n_finished) {
+  if (!pk) return fail(PF_ERR_INVALID_ARG, "null pack");
+  if (rounds < 0) return fail(PF_ERR_INVALID_ARG, "rounds must be >= 0");
+  pf_status st;
+  if (pk->dirty && (st = rebuild_pack(pk)) != PF_OK) return st;
+  if (pk->exec)
+    for (int64_t r = 0; r < rounds; ++r) PF_HIP(hipGraphLaunch(pk->exec, pk->stream));
+  if (n_finished) {
+    PF_HIP(hipStreamSynchronize(pk->stream));
+    int32_t fin = 0;
+    for (pf_domain* d : pk->members) {
+      int64_t left = 0;
+      PF_HIP(hipMemcpy(&left, reinterpret_cast<char*>(d->dev) + offsetof(DevDomain, steps_left),
+                       sizeof(left), hipMemcpyDeviceToHost));
+      fin += left == 0;
+    }
+    *n_finished = fin;
+  }
+  return PF_OK;
+}
+
+pf_status pf_pack_sync(pf_pack* pk) {
+  if (!pk) return fail(PF_ERR_INVALID_ARG, "null pack");
+  PF_HIP(hipStreamSynchronize(pk->stream));
+  return PF_OK;
+}
+
+void pf_pack_destroy(pf_pack* pk) {
+  if (!pk) return;
+  (void)hipStreamSynchronize(pk->stream);
+  for (pf_domain* d : pk->members) d->pack = nullptr;
+  drop_graph(pk);
+  if (pk->dev_ptrs) (void)hipFree(pk->dev_ptrs);
+  delete pk;
+}
+
+}  // extern "C"
