@@ -1,0 +1,171 @@
+"""Benchmark of the phase-field time step (phi-sweep + mu-sweep) on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1]
+                    [--variant 0|1] [--no-cpu] [--no-fp32]
+
+Headline: the FP64 256x256x512 domain (64 Voronoi seeds, 128 solid layers,
+synthetic parameter set P0, dt a quarter of the stability bound).  One step
+is the prologue, the phi-sweep and the mu-sweep (Algorithm 1 of the paper)
+with fields resident in HBM.  Also reported: the FP32 512x512x1024
+anisotropic domain, and the FP64 CPU oracle timed on a bounded sample of the
+headline workload on the host's cores.
+
+Prints one JSON line.  MLUP/s = cells * steps / seconds / 1e6 (the paper's
+unit, Sec. 5).  Roofline: algorithmic bytes of the dominant kernel per
+launch (phi-sweep reads phi, mu and writes phi: 10 values per cell;
+mu-sweep reads phi^n, phi^{n+1}, mu and writes mu: 12 values per cell)
+divided by its average HIP-event duration, against 8 TB/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VALUES_PER_CELL = {"phi": 10, "mu": 12}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(workload: str, steps: int, warmup: int, variant: int) -> dict:
+    import torch
+
+    import paper_1506_01684_amd as pf
+    import pfinputs
+
+    w = pfinputs.workload(workload)
+    nz, ny, nx = w["shape"]
+    cells = nx * ny * nz
+    pf.set_variant(variant)
+    d = pf.Domain(w["shape"], w["prec"])
+    d.set_params(w["params"])
+    d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
+    _log(f"[bench] {workload}: {nx}x{ny}x{nz} {w['prec']} dt={d.dt:.6g} warmup {warmup}")
+    d.step(warmup)
+    d.sync()
+    torch.cuda.synchronize()
+    _log(f"[bench] {workload}: timing {steps} steps")
+    t0 = time.perf_counter()
+    phi_ms, mu_ms = d.step_timed(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    diag = d.diagnostics()
+    d.close()
+    esize = 8 if w["prec"] == "fp64" else 4
+    out = {
+        "workload": workload, "shape": [nx, ny, nz], "prec": w["prec"], "cells": cells,
+        "steps": steps, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+        "mlups": cells * steps / wall / 1e6,
+        "phi_ms": phi_ms / steps, "mu_ms": mu_ms / steps,
+        "nonfinite": diag["nonfinite"], "max_simplex_dev": diag["max_simplex_dev"],
+    }
+    for k in ("phi", "mu"):
+        bytes_launch = VALUES_PER_CELL[k] * esize * cells
+        gbs = bytes_launch / (out[f"{k}_ms"] * 1e-3) / 1e9
+        out[f"{k}_gbs"] = gbs
+        out[f"{k}_bytes_per_launch"] = bytes_launch
+    step_bytes = (VALUES_PER_CELL["phi"] + VALUES_PER_CELL["mu"]) * esize * cells
+    out["step_hbm_frac"] = step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+def run_cpu_baseline(workload: str, budget_s: float = 20.0) -> dict:
+    """The FP64 oracle (as it stands) on the host's cores, on a bounded sample:
+    full steps of the headline domain from its Voronoi initial state."""
+    import oracle
+    import pfinputs
+
+    w = pfinputs.workload(workload)
+    shape = w["shape"]
+    p = pfinputs.with_dt(w["params"], oracle.default_dt(w["params"], shape))
+    threads = oracle.default_threads()
+    phi, mu = oracle.init_voronoi(shape, w["seed"], w["nseeds"], w["solid_height"])
+    cells = shape[0] * shape[1] * shape[2]
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        phi, mu = oracle.run(p, phi, mu, 1, step0=n, nthreads=threads)
+        n += 1
+        el = time.perf_counter() - t0
+        if el * (n + 1) / n > budget_s:
+            break
+    return {
+        "value": cells * n / el / 1e6, "unit": "MLUP/s", "cores": threads, "kind": "oracle",
+        "sample": f"{n} full step(s) of the {shape[2]}x{shape[1]}x{shape[0]} FP64 domain "
+                  f"from its Voronoi state, z planes split over {threads} threads, {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--variant", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    main_run = run_gpu(args.workload, args.steps, args.warmup, args.variant)
+    dom = "mu" if main_run["mu_ms"] >= main_run["phi_ms"] else "phi"
+    achieved = main_run[f"{dom}_gbs"]
+    line = {
+        "metric": "MLUP/s of phi+mu step (FP32 vs FP64) + %HBM peak",
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_run["prec"] == "fp64" else "f32",
+        "data": "synthetic (Voronoi-seeded solid lamellae under liquid, parameter set P0)",
+        "config": {
+            "workload": f"{args.workload}: {'x'.join(map(str, main_run['shape']))} cells, "
+                        f"{main_run['prec']}, N=4 phases, K-1=2 mu, plain method",
+            "cells": main_run["cells"], "variant": args.variant,
+            "hbm_frac_step": round(main_run["step_hbm_frac"], 4),
+            "phi_sweep_ms": round(main_run["phi_ms"], 4), "mu_sweep_ms": round(main_run["mu_ms"], 4),
+            "phi_sweep_gbs": round(main_run["phi_gbs"], 1), "mu_sweep_gbs": round(main_run["mu_gbs"], 1),
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": f"{dom}_sweep",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": main_run[f"{dom}_bytes_per_launch"],
+        },
+    }
+    if not args.no_fp32 and args.workload == "c2":
+        r32 = run_gpu("c3", args.fp32_steps, 5, args.variant)
+        line["fp32"] = {
+            "workload": "c3: 512x512x1024 cells, fp32 bulk, cubic anisotropy 0.05",
+            "mlups": round(r32["mlups"], 1), "ms_per_step": round(r32["ms_per_step"], 4),
+            "hbm_frac_step": round(r32["step_hbm_frac"], 4),
+            "phi_sweep_ms": round(r32["phi_ms"], 4), "mu_sweep_ms": round(r32["mu_ms"], 4),
+            "phi_sweep_gbs": round(r32["phi_gbs"], 1), "mu_sweep_gbs": round(r32["mu_gbs"], 1),
+            "steps": args.fp32_steps,
+        }
+    if not args.no_cpu:
+        _log("[bench] timing the CPU oracle")
+        line["cpu_baseline"] = run_cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,6 +20,9 @@ struct Geo {
   __device__ __forceinline__ int ym(int y) const { return y == 0 ? ny - 1 : y - 1; }
   __device__ __forceinline__ int zp(int z) const { return z + 1 >= nz ? nz - 1 : z + 1; }
   __device__ __forceinline__ int zm(int z) const { return z <= 0 ? 0 : z - 1; }
+  // plane p with one mirrored ghost plane on each side: -1 -> 0, nz -> nz-1
+  // (planes further out are clamped too; they are loaded but never used)
+  __device__ __forceinline__ int zc(int p) const { return p < 0 ? 0 : (p >= nz ? nz - 1 : p); }
   __device__ __forceinline__ int64_t at(int x, int y, int z) const {
     return (int64_t)z * plane + (int64_t)y * pitch + x;
   }

@@ -165,6 +165,7 @@ struct pf_domain {
   int64_t since_diag = 0;
   bool diag_pending = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> timing_events;
   pf_pack* pack = nullptr;
 
   char* fields(int copy) const { return base + L.off_fields + (size_t)copy * L.copy_bytes; }
@@ -543,13 +544,22 @@ pf_status pf_step_timed(pf_domain* d, int64_t n, double* phi_ms, double* mu_ms) 
   if (st != PF_OK) return st;
   if (n < 0) return fail(PF_ERR_INVALID_ARG, "n must be >= 0");
   if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
+  // three events per step, all read after the last step, so the steps run
+  // back to back exactly as in pf_step
+  while (d->timing_events.size() < (size_t)(3 * n)) {
+    hipEvent_t e;
+    PF_HIP(hipEventCreate(&e));
+    d->timing_events.push_back(e);
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if ((st = enqueue_step(d, d->timing_events.data() + 3 * i)) != PF_OK) return st;
   double tp = 0.0, tm = 0.0;
+  if (n > 0) PF_HIP(hipEventSynchronize(d->timing_events[3 * n - 1]));
   for (int64_t i = 0; i < n; ++i) {
-    if ((st = enqueue_step(d, d->ev)) != PF_OK) return st;
-    PF_HIP(hipEventSynchronize(d->ev[2]));
     float a = 0.f, b = 0.f;
-    PF_HIP(hipEventElapsedTime(&a, d->ev[0], d->ev[1]));
-    PF_HIP(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
+    hipEvent_t* e = d->timing_events.data() + 3 * i;
+    PF_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+    PF_HIP(hipEventElapsedTime(&b, e[1], e[2]));
     tp += a;
     tm += b;
   }
@@ -634,6 +644,7 @@ void pf_destroy(pf_domain* d) {
   (void)hipStreamSynchronize(d->stream);
   for (auto& e : d->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : d->timing_events) (void)hipEventDestroy(e);
   if (d->owned && d->base) (void)hipFree(d->base);
   delete d;
 }

@@ -1,14 +1,511 @@
-// pf_tiled.hip -- face-sharing z-marching variant of the sweeps (in progress).
+// pf_tiled.hip -- face-sharing z-marching variant of the two sweeps.
+//
+// A work group of 256 threads owns an x-y tile (64x4 or 32x8 columns) and
+// marches over a chunk of z planes.  The phi^n planes it needs are staged in
+// LDS with a one-cell halo ring (one plane for the isotropic phi-sweep,
+// a ring of three planes k-1, k, k+1 when tangential face gradients are
+// needed: anisotropic phi-sweep and the mu-sweep's anti-trapping current).
+// Every face of the tile is evaluated once (Sec. 3.3 buffers staggered
+// values so each is computed once; here a z face lives in registers from
+// one plane to the next and x/y faces are exchanged through LDS):
+//   - each thread evaluates the upper x and y faces of its column and the
+//     z face above its cell;
+//   - the tile's lower-edge x and y faces are evaluated by the first
+//     threads, through the same code path as all other faces of that
+//     direction, so every face rounds identically wherever it is computed;
+//   - the next plane's loads are issued before the face stage and written
+//     to LDS after it, so their latency overlaps the arithmetic.
 #include <hip/hip_runtime.h>
 
+#include "pf_device.h"
 #include "pf_kernels_common.h"
 #include "pf_launch.h"
 
 namespace pfk {
 
-hipError_t launch_phi_tiled(const LaunchSet&, int, bool, hipStream_t) {
-  return hipErrorNotSupported;
+template <typename R>
+struct alignas(4 * sizeof(R)) V4 {
+  R v[4];
+};
+
+constexpr int kMaxHalo = 400;  // (tx+2)(ty+2): 66*6 = 396, 34*10 = 340
+constexpr int kMaxFx = 264;    // ty (tx+1): 4*65 = 260, 8*33 = 264
+constexpr int kMaxFy = 320;    // (ty+1) tx: 5*64 = 320, 9*32 = 288
+
+// Per-item geometry of one thread.
+struct TileGeo {
+  int tx, ty, lx, ly, x0, y0, z0, z1;
+  bool valid;
+  int own_c;        // LDS index of the own column
+  int64_t own_off;  // in-plane offset of the own column (wrapped for idle threads)
+  int halo_c;       // LDS index of the halo cell this thread loads (-1: none)
+  int64_t halo_off;
+  __device__ __forceinline__ int ci(int cx, int cy) const { return cy * (tx + 2) + cx; }
+};
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
 }
-hipError_t launch_mu_tiled(const LaunchSet&, int, hipStream_t) { return hipErrorNotSupported; }
+
+__device__ __forceinline__ TileGeo make_tile(const DevDomain& d, int local, int t) {
+  TileGeo G;
+  const WorkTile w = decode_item(d, local, t);
+  G.tx = d.tx;
+  G.ty = d.ty;
+  G.lx = w.lx;
+  G.ly = w.ly;
+  G.x0 = w.x0;
+  G.y0 = w.y0;
+  G.z0 = w.z0;
+  G.z1 = w.z1;
+  G.valid = w.valid;
+  G.own_c = G.ci(w.lx + 1, w.ly + 1);
+  const int gx = wrap_mod(w.x, d.nx), gy = wrap_mod(w.y, d.ny);
+  G.own_off = (int64_t)gy * d.pitch + gx;
+  const int nhalo = 2 * (G.tx + 2) + 2 * G.ty;
+  G.halo_c = -1;
+  G.halo_off = 0;
+  if (t < nhalo) {
+    int cx, cy;
+    if (t < G.tx + 2) {
+      cx = t;
+      cy = 0;
+    } else if (t < 2 * (G.tx + 2)) {
+      cx = t - (G.tx + 2);
+      cy = G.ty + 1;
+    } else if (t < 2 * (G.tx + 2) + G.ty) {
+      cx = 0;
+      cy = t - 2 * (G.tx + 2) + 1;
+    } else {
+      cx = G.tx + 1;
+      cy = t - 2 * (G.tx + 2) - G.ty + 1;
+    }
+    G.halo_c = G.ci(cx, cy);
+    const int hx = wrap_mod(G.x0 - 1 + cx, d.nx), hy = wrap_mod(G.y0 - 1 + cy, d.ny);
+    G.halo_off = (int64_t)hy * d.pitch + hx;
+  }
+  return G;
+}
+
+template <typename R>
+__device__ __forceinline__ V4<R> load4(const R* base, int64_t fstride, int64_t off) {
+  V4<R> v;
+#pragma unroll
+  for (int a = 0; a < NP; ++a) v.v[a] = base[a * fstride + off];
+  return v;
+}
+
+__device__ __forceinline__ int slot_of(int nslot, int plane) {
+  return nslot == 1 ? 0 : (plane + 3) % 3;
+}
+
+// Face inputs from LDS: face between LDS cells (cx,cy) and its upper
+// neighbour along D, planes given by slots (sm, s0, sp) = (k-1, k, k+1) for
+// x/y faces, (s0, sp) = (k, k+1) for z faces.  FULL adds the tangential
+// components (4-point averages of central differences).
+template <typename R, int D, bool FULL>
+__device__ __forceinline__ void lds_face(const V4<R> (*S)[kMaxHalo], const TileGeo& G, int cx,
+                                         int cy, int sm, int s0, int sp, R inv_dx, R inv_4dx,
+                                         R pb[NP], R gn[NP], R gt1[NP], R gt2[NP]) {
+  const int cL = G.ci(cx, cy);
+  const int cU = D == 0 ? G.ci(cx + 1, cy) : (D == 1 ? G.ci(cx, cy + 1) : cL);
+  const V4<R> L = S[s0][cL];
+  const V4<R> U = D == 2 ? S[sp][cL] : S[s0][cU];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    pb[a] = R(0.5) * (L.v[a] + U.v[a]);
+    gn[a] = (U.v[a] - L.v[a]) * inv_dx;
+    gt1[a] = gt2[a] = R(0);
+  }
+  if constexpr (FULL) {
+    V4<R> p1L, p1U, m1L, m1U, p2L, p2U, m2L, m2U;
+    if constexpr (D == 0) {  // tangential y (in plane), z (slots)
+      p1L = S[s0][G.ci(cx, cy + 1)];
+      p1U = S[s0][G.ci(cx + 1, cy + 1)];
+      m1L = S[s0][G.ci(cx, cy - 1)];
+      m1U = S[s0][G.ci(cx + 1, cy - 1)];
+      p2L = S[sp][cL];
+      p2U = S[sp][cU];
+      m2L = S[sm][cL];
+      m2U = S[sm][cU];
+    } else if constexpr (D == 1) {  // tangential x, z
+      p1L = S[s0][G.ci(cx + 1, cy)];
+      p1U = S[s0][G.ci(cx + 1, cy + 1)];
+      m1L = S[s0][G.ci(cx - 1, cy)];
+      m1U = S[s0][G.ci(cx - 1, cy + 1)];
+      p2L = S[sp][cL];
+      p2U = S[sp][cU];
+      m2L = S[sm][cL];
+      m2U = S[sm][cU];
+    } else {  // tangential x, y; L in plane k (s0), U in plane k+1 (sp)
+      p1L = S[s0][G.ci(cx + 1, cy)];
+      p1U = S[sp][G.ci(cx + 1, cy)];
+      m1L = S[s0][G.ci(cx - 1, cy)];
+      m1U = S[sp][G.ci(cx - 1, cy)];
+      p2L = S[s0][G.ci(cx, cy + 1)];
+      p2U = S[sp][G.ci(cx, cy + 1)];
+      m2L = S[s0][G.ci(cx, cy - 1)];
+      m2U = S[sp][G.ci(cx, cy - 1)];
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      gt1[a] = ((p1L.v[a] + p1U.v[a]) - (m1L.v[a] + m1U.v[a])) * inv_4dx;
+      gt2[a] = ((p2L.v[a] + p2U.v[a]) - (m2L.v[a] + m2U.v[a])) * inv_4dx;
+    }
+  }
+}
+
+// ============================================================ phi-sweep
+
+template <typename R, bool ANISO>
+__global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* const* doms,
+                                                                 const int32_t* first, int ndom,
+                                                                 int total) {
+  constexpr int NSLOT = ANISO ? 3 : 1;
+  constexpr int AHEAD = ANISO ? 2 : 1;  // plane loaded during iteration k: k + AHEAD
+  __shared__ V4<R> s_phi[NSLOT][kMaxHalo];
+  __shared__ R s_fx[kMaxFx][2 * NP];  // F[0..3], S[0..3]
+  __shared__ R s_fy[kMaxFy][2 * NP];
+  const int t = threadIdx.x;
+
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int di = find_domain(first, ndom, item);
+    const DevDomain& d = *doms[di];
+    if (!d.active) continue;  // uniform over the work group
+    const TileGeo G = make_tile(d, item - first[di], t);
+    const Geo g = make_geo(d);
+    const KParams<R>& P = kparams<R>(d);
+    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
+    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
+    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
+    const R* mu0 = src + 4 * d.fstride;
+    const R* mu1 = src + 5 * d.fstride;
+    const int64_t fs = d.fstride;
+    const int kstart = G.z0 - 1;
+
+    // prime the LDS ring with planes kstart-1 .. kstart+AHEAD-1 (NSLOT planes)
+    for (int p = kstart - (NSLOT == 3 ? 1 : 0); p <= kstart + (NSLOT == 3 ? 1 : 0); ++p) {
+      const int64_t po = (int64_t)g.zc(p) * d.plane;
+      const int sl = slot_of(NSLOT, p);
+      s_phi[sl][G.own_c] = load4(src, fs, po + G.own_off);
+      if (G.halo_c >= 0) s_phi[sl][G.halo_c] = load4(src, fs, po + G.halo_off);
+    }
+    V4<R> own_k = load4(src, fs, (int64_t)g.zc(kstart) * d.plane + G.own_off);
+    __syncthreads();
+
+    R Fzl[NP], Szl[NP];  // z face below the current plane
+#pragma unroll
+    for (int a = 0; a < NP; ++a) Fzl[a] = Szl[a] = R(0);
+
+    for (int k = kstart; k < G.z1; ++k) {
+      const bool cells = k >= G.z0;  // kstart only evaluates the z face above it
+      const int sm = slot_of(NSLOT, k - 1), s0 = slot_of(NSLOT, k), sp = slot_of(NSLOT, k + 1);
+      // issue the loads of plane k+AHEAD (own column and halo cell)
+      const int64_t pa = (int64_t)g.zc(k + AHEAD) * d.plane;
+      const V4<R> nxt_own = load4(src, fs, pa + G.own_off);
+      V4<R> nxt_halo;
+      if (G.halo_c >= 0) nxt_halo = load4(src, fs, pa + G.halo_off);
+      R mc[NM] = {R(0), R(0)};
+      if (cells) {
+        const int64_t o = (int64_t)k * d.plane + G.own_off;
+        mc[0] = mu0[o];
+        mc[1] = mu1[o];
+        // x faces: own upper face, plus the tile's lower edge face for the
+        // first ty threads (same code path for both)
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          const bool edge = r == 1;
+          if (edge ? !(t < G.ty && G.y0 + t < g.ny) : !G.valid) continue;
+          const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
+          const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
+          R pb[NP], gn[NP], gt1[NP], gt2[NP], F[NP], S[NP];
+          lds_face<R, 0, ANISO>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+          phi_face<R, ANISO, 0>(P, pb, gn, gt1, gt2, F, S);
+#pragma unroll
+          for (int a = 0; a < NP; ++a) {
+            s_fx[fo][a] = F[a];
+            s_fx[fo][NP + a] = S[a];
+          }
+        }
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          const bool edge = r == 1;
+          if (edge ? !(t < G.tx && G.x0 + t < g.nx) : !G.valid) continue;
+          const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
+          const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
+          R pb[NP], gn[NP], gt1[NP], gt2[NP], F[NP], S[NP];
+          lds_face<R, 1, ANISO>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+          phi_face<R, ANISO, 1>(P, pb, gn, gt1, gt2, F, S);
+#pragma unroll
+          for (int a = 0; a < NP; ++a) {
+            s_fy[fo][a] = F[a];
+            s_fy[fo][NP + a] = S[a];
+          }
+        }
+      }
+      // z face above plane k (zero on the z boundaries)
+      R Fzu[NP], Szu[NP];
+      if (k < 0 || k >= g.nz - 1) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) Fzu[a] = Szu[a] = R(0);
+      } else {
+        R pb[NP], gn[NP], gt1[NP], gt2[NP];
+        if constexpr (ANISO) {
+          lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, P.inv_dx, P.inv_4dx, pb,
+                               gn, gt1, gt2);
+        } else {
+          // own column at k (registers) and k+1 (just loaded)
+#pragma unroll
+          for (int a = 0; a < NP; ++a) {
+            pb[a] = R(0.5) * (own_k.v[a] + nxt_own.v[a]);
+            gn[a] = (nxt_own.v[a] - own_k.v[a]) * P.inv_dx;
+            gt1[a] = gt2[a] = R(0);
+          }
+        }
+        phi_face<R, ANISO, 2>(P, pb, gn, gt1, gt2, Fzu, Szu);
+      }
+      __syncthreads();  // B1: faces visible; LDS plane slots of k-1 (or k) free
+      {
+        const int sl = slot_of(NSLOT, k + AHEAD);
+        s_phi[sl][G.own_c] = nxt_own;
+        if (G.halo_c >= 0) s_phi[sl][G.halo_c] = nxt_halo;
+      }
+      if (cells && G.valid) {
+        const int fl = G.ly * (G.tx + 1) + G.lx;  // lower x face; upper is fl+1
+        const int yl = G.ly * G.tx + G.lx;        // lower y face; upper is yl+tx
+        R Ss[NP], Fd[NP], pc[NP];
+        V4<R> ownv;
+        if constexpr (ANISO) ownv = s_phi[s0][G.own_c];
+        else ownv = own_k;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          pc[a] = ownv.v[a];
+          Ss[a] = R(0);
+          Fd[a] = R(0);
+          Ss[a] += s_fx[fl + 1][NP + a] + s_fx[fl][NP + a];
+          Fd[a] += s_fx[fl + 1][a] - s_fx[fl][a];
+          Ss[a] += s_fy[yl + G.tx][NP + a] + s_fy[yl][NP + a];
+          Fd[a] += s_fy[yl + G.tx][a] - s_fy[yl][a];
+          Ss[a] += Szu[a] + Szl[a];
+          Fd[a] += Fzu[a] - Fzl[a];
+        }
+        double out[NP];
+        phi_cell<R>(P, tab[k], pc, mc, Ss, Fd, out);
+        const int64_t o = (int64_t)k * d.plane + G.own_off;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) dst[a * fs + o] = (R)out[a];
+      }
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        Fzl[a] = Fzu[a];
+        Szl[a] = Szu[a];
+      }
+      if constexpr (!ANISO) own_k = nxt_own;
+      __syncthreads();  // B2: LDS plane and faces consumed
+    }
+  }
+}
+
+// ============================================================= mu-sweep
+
+template <typename R>
+__global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const* doms,
+                                                                const int32_t* first, int ndom,
+                                                                int total) {
+  constexpr int NSLOT = 3, AHEAD = 2;
+  __shared__ V4<R> s_phi[NSLOT][kMaxHalo];
+  __shared__ R s_fx[kMaxFx][NM];
+  __shared__ R s_fy[kMaxFy][NM];
+  const int t = threadIdx.x;
+
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int di = find_domain(first, ndom, item);
+    const DevDomain& d = *doms[di];
+    if (!d.active) continue;
+    const TileGeo G = make_tile(d, item - first[di], t);
+    const Geo g = make_geo(d);
+    const KParams<R>& P = kparams<R>(d);
+    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
+    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
+    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
+    const int64_t fs = d.fstride;
+    const R* p1 = dst;  // phi^{n+1}, written by the phi-sweep
+    const R* mu0 = src + 4 * fs;
+    const R* mu1 = src + 5 * fs;
+    R* mo0 = dst + 4 * fs;
+    R* mo1 = dst + 5 * fs;
+    const int kstart = G.z0 - 1;
+
+    if (P.mu_frozen) {  // mu^{n+1} = mu^n (tests of the phi part only)
+      if (G.valid)
+        for (int k = G.z0; k < G.z1; ++k) {
+          const int64_t o = (int64_t)k * d.plane + G.own_off;
+          mo0[o] = mu0[o];
+          mo1[o] = mu1[o];
+        }
+      continue;
+    }
+
+    // in-plane offsets of the face partners (x+1 / y+1 of the own column;
+    // the tile's lower-edge faces use x0-1 / y0-1)
+    const int gx = G.x0 + G.lx, gy = G.y0 + G.ly;
+    const int64_t off_xu = G.valid ? (int64_t)gy * d.pitch + g.xp(gx) : G.own_off;
+    const int64_t off_yu = G.valid ? (int64_t)g.yp(gy) * d.pitch + gx : G.own_off;
+    int64_t edge_xL = 0, edge_xU = 0, edge_yL = 0, edge_yU = 0;
+    const bool ex = t < G.ty && G.y0 + t < g.ny;
+    const bool ey = t < G.tx && G.x0 + t < g.nx;
+    if (ex) {
+      edge_xL = (int64_t)(G.y0 + t) * d.pitch + g.xm(G.x0);
+      edge_xU = (int64_t)(G.y0 + t) * d.pitch + G.x0;
+    }
+    if (ey) {
+      edge_yL = (int64_t)g.ym(G.y0) * d.pitch + G.x0 + t;
+      edge_yU = (int64_t)G.y0 * d.pitch + G.x0 + t;
+    }
+
+    for (int p = kstart - 1; p <= kstart + 1; ++p) {
+      const int64_t po = (int64_t)g.zc(p) * d.plane;
+      const int sl = slot_of(NSLOT, p);
+      s_phi[sl][G.own_c] = load4(src, fs, po + G.own_off);
+      if (G.halo_c >= 0) s_phi[sl][G.halo_c] = load4(src, fs, po + G.halo_off);
+    }
+    // phi^{n+1} and mu^n of the own column at plane kstart
+    int64_t ok = (int64_t)g.zc(kstart) * d.plane + G.own_off;
+    V4<R> own1 = load4(p1, fs, ok);
+    R ownm[NM] = {mu0[ok], mu1[ok]};
+    __syncthreads();
+
+    R Pzl[NM] = {R(0), R(0)};
+    for (int k = kstart; k < G.z1; ++k) {
+      const bool cells = k >= G.z0;
+      const int sm = slot_of(NSLOT, k - 1), s0 = slot_of(NSLOT, k), sp = slot_of(NSLOT, k + 1);
+      const int64_t pa = (int64_t)g.zc(k + AHEAD) * d.plane;
+      const V4<R> nxt_own = load4(src, fs, pa + G.own_off);
+      V4<R> nxt_halo;
+      if (G.halo_c >= 0) nxt_halo = load4(src, fs, pa + G.halo_off);
+      // own column at k+1: phi^{n+1}, mu^n (for the z face above k)
+      const int64_t o1 = (int64_t)g.zp(k) * d.plane + G.own_off;
+      const V4<R> up1 = load4(p1, fs, o1);
+      const R upm[NM] = {mu0[o1], mu1[o1]};
+      const int64_t pk = (int64_t)(k < 0 ? 0 : k) * d.plane;
+      const PlaneCoef<R>& C = tab[k < 0 ? 0 : k];
+      if (cells) {
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          const bool edge = r == 1;
+          if (edge ? !ex : !G.valid) continue;
+          const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
+          const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
+          const int64_t oL = pk + (edge ? edge_xL : G.own_off);
+          const int64_t oU = pk + (edge ? edge_xU : off_xu);
+          R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3], mL[NM], mU[NM], Phi[NM];
+          lds_face<R, 0, true>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+          const V4<R> L0 = s_phi[s0][G.ci(cx, cy)], U0 = s_phi[s0][G.ci(cx + 1, cy)];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            dph[a] = (p1[a * fs + oL] - L0.v[a]) + (p1[a * fs + oU] - U0.v[a]);
+          mL[0] = mu0[oL];
+          mL[1] = mu1[oL];
+          mU[0] = mu0[oU];
+          mU[1] = mu1[oU];
+          mu_face<R, 0>(P, C.Dchi, C.dchiL, C.dcbL, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          s_fx[fo][0] = Phi[0];
+          s_fx[fo][1] = Phi[1];
+        }
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          const bool edge = r == 1;
+          if (edge ? !ey : !G.valid) continue;
+          const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
+          const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
+          const int64_t oL = pk + (edge ? edge_yL : G.own_off);
+          const int64_t oU = pk + (edge ? edge_yU : off_yu);
+          R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3], mL[NM], mU[NM], Phi[NM];
+          lds_face<R, 1, true>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+          const V4<R> L0 = s_phi[s0][G.ci(cx, cy)], U0 = s_phi[s0][G.ci(cx, cy + 1)];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            dph[a] = (p1[a * fs + oL] - L0.v[a]) + (p1[a * fs + oU] - U0.v[a]);
+          mL[0] = mu0[oL];
+          mL[1] = mu1[oL];
+          mU[0] = mu0[oU];
+          mU[1] = mu1[oU];
+          mu_face<R, 1>(P, C.Dchi, C.dchiL, C.dcbL, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          s_fy[fo][0] = Phi[0];
+          s_fy[fo][1] = Phi[1];
+        }
+      }
+      // z face above plane k
+      R Pzu[NM] = {R(0), R(0)};
+      if (k >= 0 && k < g.nz - 1) {
+        R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3];
+        lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn,
+                             gt1, gt2);
+        const V4<R> L0 = s_phi[s0][G.own_c], U0 = s_phi[sp][G.own_c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
+        mu_face<R, 2>(P, C.DchiZ, C.dchiLZ, C.dcbLZ, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+      }
+      V4<R> own0;
+      if (cells) own0 = s_phi[s0][G.own_c];
+      __syncthreads();  // B1
+      {
+        const int sl = slot_of(NSLOT, k + AHEAD);
+        s_phi[sl][G.own_c] = nxt_own;
+        if (G.halo_c >= 0) s_phi[sl][G.halo_c] = nxt_halo;
+      }
+      if (cells && G.valid) {
+        const int fl = G.ly * (G.tx + 1) + G.lx;
+        const int yl = G.ly * G.tx + G.lx;
+        R div[NM], out[NM];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          div[q] = R(0);
+          div[q] += s_fx[fl + 1][q] - s_fx[fl][q];
+          div[q] += s_fy[yl + G.tx][q] - s_fy[yl][q];
+          div[q] = (div[q] + (Pzu[q] - Pzl[q])) * P.inv_dx;
+        }
+        mu_cell<R>(P, C, own0.v, own1.v, ownm, div, out);
+        const int64_t o = (int64_t)k * d.plane + G.own_off;
+        mo0[o] = out[0];
+        mo1[o] = out[1];
+      }
+      Pzl[0] = Pzu[0];
+      Pzl[1] = Pzu[1];
+      own1 = up1;
+      ownm[0] = upm[0];
+      ownm[1] = upm[1];
+      __syncthreads();  // B2
+    }
+  }
+}
+
+// --------------------------------------------------------------- launches
+
+hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
+  const int grid = L.total;
+  if (prec == 0) {
+    if (aniso)
+      phi_tiled_kernel<double, true><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    else
+      phi_tiled_kernel<double, false><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  } else {
+    if (aniso)
+      phi_tiled_kernel<float, true><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    else
+      phi_tiled_kernel<float, false><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mu_tiled(const LaunchSet& L, int prec, hipStream_t s) {
+  const int grid = L.total;
+  if (prec == 0)
+    mu_tiled_kernel<double><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  else
+    mu_tiled_kernel<float><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  return hipGetLastError();
+}
 
 }  // namespace pfk
