@@ -114,7 +114,20 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times "
+                         "(reference for the FETCH_SIZE/WRITE_SIZE counter scale)")
     args = ap.parse_args()
+    if args.calibrate_copy > 0:
+        import torch
+
+        a = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy, "repeats": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding is described, not built)", file=sys.stderr)

@@ -14,7 +14,24 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Address spaces of gfx9: 1 = global (vector memory), 4 = constant (read
+// only for the duration of a kernel; loads with a uniform address become
+// scalar loads).  Field pointers are cast to global so loads are not flat
+// loads; descriptors and per-plane coefficient tables, written only by other
+// kernels, are read through the constant space.
+#define PF_GLOBAL __attribute__((address_space(1)))
+#define PF_CONST __attribute__((address_space(4)))
+
 namespace pfk {
+
+template <typename T>
+__device__ __forceinline__ const PF_CONST T* to_const(const T* p) {
+  return (const PF_CONST T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ PF_GLOBAL T* to_global(T* p) {
+  return (PF_GLOBAL T*)(p);
+}
 
 constexpr int NP = 4;   // phases
 constexpr int NM = 2;   // chemical potentials
@@ -85,27 +102,34 @@ struct DevDomain {
   KParams<float> kp32;
 };
 
-template <typename R>
-__device__ __forceinline__ const KParams<R>& kparams(const DevDomain& d);
-template <>
-__device__ __forceinline__ const KParams<double>& kparams<double>(const DevDomain& d) {
-  return d.kp64;
-}
-template <>
-__device__ __forceinline__ const KParams<float>& kparams<float>(const DevDomain& d) {
-  return d.kp32;
+template <typename R, typename DD>
+__device__ __forceinline__ const auto& kparams(const DD& d) {
+  if constexpr (sizeof(R) == 8) return d.kp64;
+  else return d.kp32;
 }
 
 // ------------------------------------------------------------ math helpers
+//
+// FP64: hardware reciprocal / reciprocal square root refined by two Newton
+// steps (relative error about one ulp); FP32: the hardware instructions
+// (about one ulp).  Arguments are positive and normal wherever they are used.
 
-__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rcp_(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double rsq_(double x) { return 1.0 / __builtin_sqrt(x); }
+__device__ __forceinline__ double rsq_(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double e = __builtin_fma(-x * r, r, 1.0);
+  r = __builtin_fma(0.5 * r, e, r);
+  e = __builtin_fma(-x * r, r, 1.0);
+  return __builtin_fma(0.5 * r, e, r);
+}
 __device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double div_(double a, double b) { return a / b; }
-__device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // --------------------------------------------------------- phi face stage
 
@@ -118,8 +142,8 @@ __device__ __forceinline__ R aniso_Xd(R qx, R qy, R qz, R delta) {
   const R q[3] = {qx, qy, qz};
   R qq = qx * qx + qy * qy + qz * qz;
   if (delta == R(0) || qq <= R(1e-30)) return R(2) * q[D];
-  R qn = sqrt_(qq);
-  R inv = rcp_(qn);
+  R inv = rsq_(qq);
+  R qn = qq * inv;
   R hx = qx * inv, hy = qy * inv, hz = qz * inv;
   R P = (hx * hx) * (hx * hx) + (hy * hy) * (hy * hy) + (hz * hz) * (hz * hz);
   R ac = R(1) - delta * (R(3) - R(4) * P);
@@ -134,8 +158,8 @@ __device__ __forceinline__ R aniso_Xd(R qx, R qy, R qz, R delta) {
 //  gt1/gt2 tangential components (only read when ANISO)
 // Outputs F_a = sum_{b!=a} gamma_ab (-pb_b) X_ab.e_D  and
 //         S_a = sum_{b!=a} gamma_ab  X_ab.e_D (gn_b),  X_ba = -X_ab.
-template <typename R, bool ANISO, int D>
-__device__ __forceinline__ void phi_face(const KParams<R>& P, const R pb[NP], const R gn[NP],
+template <typename R, bool ANISO, int D, typename KP>
+__device__ __forceinline__ void phi_face(const KP& P, const R pb[NP], const R gn[NP],
                                          const R gt1[NP], const R gt2[NP], R F[NP], R S[NP]) {
 #pragma unroll
   for (int a = 0; a < NP; ++a) F[a] = S[a] = R(0);
@@ -154,9 +178,9 @@ __device__ __forceinline__ void phi_face(const KParams<R>& P, const R pb[NP], co
         if constexpr (D == 0) { qx = qn; qy = q1; qz = q2; }
         else if constexpr (D == 1) { qx = q1; qy = qn; qz = q2; }
         else { qx = q1; qy = q2; qz = qn; }
-        Y = P.g1[pi] * aniso_Xd<R, D>(qx, qy, qz, P.delta[pi]);
+        Y = (R)P.g1[pi] * aniso_Xd<R, D>(qx, qy, qz, (R)P.delta[pi]);
       } else {
-        Y = P.g2[pi] * (pb[a] * gn[b] - pb[b] * gn[a]);
+        Y = (R)P.g2[pi] * (pb[a] * gn[b] - pb[b] * gn[a]);
       }
       F[a] -= pb[b] * Y;
       F[b] += pb[a] * Y;
@@ -169,17 +193,17 @@ __device__ __forceinline__ void phi_face(const KParams<R>& P, const R pb[NP], co
 // ------------------------------------------------------------ projection
 
 // Euclidean projection of y onto {x >= 0, sum x = 1} followed by
-// renormalisation, in FP64 (sort descending, largest j with
-// u_j - (s_j - 1)/j > 0, threshold theta = (s_rho - 1)/rho, clip).
+// renormalisation, in FP64: sort descending, rho = largest j with
+// j u_j > s_j - 1 (u_j - (s_j - 1)/j > 0 multiplied by j > 0), threshold
+// theta = (s_rho - 1)/rho, clip, divide by the sum.
 __device__ __forceinline__ void project_simplex(const double y[NP], double x[NP]) {
   double u0 = y[0], u1 = y[1], u2 = y[2], u3 = y[3];
-  // sorting network, descending
-#define PF_CSWAP(a, b)        \
-  {                           \
-    double hi = fmax(a, b);   \
-    double lo = fmin(a, b);   \
-    a = hi;                   \
-    b = lo;                   \
+#define PF_CSWAP(a, b)      \
+  {                         \
+    double hi = fmax(a, b); \
+    double lo = fmin(a, b); \
+    a = hi;                 \
+    b = lo;                 \
   }
   PF_CSWAP(u0, u1);
   PF_CSWAP(u2, u3);
@@ -187,24 +211,17 @@ __device__ __forceinline__ void project_simplex(const double y[NP], double x[NP]
   PF_CSWAP(u1, u3);
   PF_CSWAP(u1, u2);
 #undef PF_CSWAP
-  double s1 = u0, s2 = s1 + u1, s3 = s2 + u2, s4 = s3 + u3;
-  // rho = largest j whose condition holds (the conditions hold on a prefix)
-  double srho = s1, rinv = 1.0;
-  int rho = 1;
-  if (u1 - (s2 - 1.0) / 2.0 > 0.0) { rho = 2; srho = s2; }
-  if (u2 - (s3 - 1.0) / 3.0 > 0.0) { rho = 3; srho = s3; }
-  if (u3 - (s4 - 1.0) / 4.0 > 0.0) { rho = 4; srho = s4; }
-  (void)rinv;
-  double theta = (srho - 1.0) / (double)rho;
+  const double s1 = u0, s2 = s1 + u1, s3 = s2 + u2, s4 = s3 + u3;
+  double theta = s1 - 1.0;
+  if (2.0 * u1 > s2 - 1.0) theta = (s2 - 1.0) * 0.5;
+  if (3.0 * u2 > s3 - 1.0) theta = (s3 - 1.0) * (1.0 / 3.0);
+  if (4.0 * u3 > s4 - 1.0) theta = (s4 - 1.0) * 0.25;
   double xs[NP];
 #pragma unroll
-  for (int a = 0; a < NP; ++a) {
-    double v = y[a] - theta;
-    xs[a] = v > 0.0 ? v : 0.0;
-  }
-  double sum = ((xs[0] + xs[1]) + xs[2]) + xs[3];
+  for (int a = 0; a < NP; ++a) xs[a] = fmax(y[a] - theta, 0.0);
+  const double inv = rcp_(((xs[0] + xs[1]) + xs[2]) + xs[3]);
 #pragma unroll
-  for (int a = 0; a < NP; ++a) x[a] = xs[a] / sum;
+  for (int a = 0; a < NP; ++a) x[a] = xs[a] * inv;
 }
 
 // -------------------------------------------------------- phi cell stage
@@ -213,22 +230,22 @@ __device__ __forceinline__ void project_simplex(const double y[NP], double x[NP]
 // obstacle derivative, the driving force (2 phi_a/S)(psi_a - sum h_b psi_b),
 // rhs_a = eps T A_a + (T/eps) omega'_a + psi'_a, Lagrange mean over the four
 // phases, explicit Euler, projection.
-template <typename R>
-__device__ __forceinline__ void phi_cell(const KParams<R>& P, const PlaneCoef<R>& C,
-                                         const R ph[NP], const R mu[NM], const R Ssum[NP],
-                                         const R Fdiff[NP], double out[NP]) {
-  // Ssum[a] = sum_d (S_up + S_low);  Fdiff[a] = sum_d (F_up - F_low)
+//   Ssum[a] = sum over directions of (S_up + S_low)
+//   Fdiff[a] = sum over directions of (F_up - F_low)
+template <typename R, typename KP, typename CP>
+__device__ __forceinline__ void phi_cell(const KP& P, const CP& C, const R ph[NP], const R mu[NM],
+                                         const R Ssum[NP], const R Fdiff[NP], double out[NP]) {
   R A[NP];
 #pragma unroll
-  for (int a = 0; a < NP; ++a) A[a] = R(0.5) * Ssum[a] - Fdiff[a] * P.inv_dx;
+  for (int a = 0; a < NP; ++a) A[a] = R(0.5) * Ssum[a] - Fdiff[a] * (R)P.inv_dx;
   R S = ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2] + ph[3] * ph[3];
   R invS = rcp_(S);
   R psi[NP], psibar = R(0);
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
-    R quad = C.chi[a][0] * mu[0] * mu[0] + C.chi[a][1] * mu[1] * mu[1];
-    R lin = C.cbar[a][0] * mu[0] + C.cbar[a][1] * mu[1];
-    psi[a] = R(-0.5) * quad - lin + C.wbar[a];
+    R quad = (R)C.chi[a][0] * mu[0] * mu[0] + (R)C.chi[a][1] * mu[1] * mu[1];
+    R lin = (R)C.cbar[a][0] * mu[0] + (R)C.cbar[a][1] * mu[1];
+    psi[a] = R(-0.5) * quad - lin + (R)C.wbar[a];
     psibar += (ph[a] * ph[a]) * psi[a];
   }
   psibar *= invS;
@@ -240,25 +257,25 @@ __device__ __forceinline__ void phi_cell(const KParams<R>& P, const PlaneCoef<R>
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       if (b == a) continue;
-      pair += P.g16[a < b ? pair_index(a, b) : pair_index(b, a)] * ph[b];
+      pair += (R)P.g16[a < b ? pair_index(a, b) : pair_index(b, a)] * ph[b];
 #pragma unroll
       for (int e = b + 1; e < NP; ++e)
         if (e != a) triple += ph[b] * ph[e];
     }
-    R domega = pair + P.gamma3 * triple;
-    rhs[a] = C.epsT * A[a] + C.Toe * domega + dpsi;
+    R domega = pair + (R)P.gamma3 * triple;
+    rhs[a] = (R)C.epsT * A[a] + (R)C.Toe * domega + dpsi;
   }
   R mean = R(0.25) * (((rhs[0] + rhs[1]) + rhs[2]) + rhs[3]);
   double y[NP];
 #pragma unroll
-  for (int a = 0; a < NP; ++a) y[a] = (double)(ph[a] - P.rate[a] * (rhs[a] - mean));
+  for (int a = 0; a < NP; ++a) y[a] = (double)(ph[a] - (R)P.rate[a] * (rhs[a] - mean));
   project_simplex(y, out);
 }
 
 // --------------------------------------------------------- mu face stage
 
-// Face stage of the mu-sweep on a face with normal D (Eq. (3) flux and
-// Eq. (4) normal component):
+// Face stage of the mu-sweep on a face with normal D (Eq. (3) flux and the
+// normal component of Eq. (4)); ZF selects the coefficients at T(k+1/2):
 //   M_i = sum_a D_a pb_a chi_ai(T_f),  diff_i = M_i (mu_i,U - mu_i,L)/dx
 //   J_i = (pi eps/4) sum_{a<3} w_a rate_a (n_a.n_l)(n_a.e_D) dc_ai
 //   w_a = sqrt(pb_a pb_l) pb_l / sum pb^2  (= g_a h_l / sqrt(phi_a phi_l))
@@ -267,27 +284,25 @@ __device__ __forceinline__ void phi_cell(const KParams<R>& P, const PlaneCoef<R>
 // pb: face average of phi^n; gn/gt1/gt2: normal and tangential face
 // gradient of phi^n; dph: (phi^{n+1}-phi^n)_L + (...)_U per solid phase;
 // mL/mU: mu^n at the face cells.
-template <typename R, int D>
-__device__ __forceinline__ void mu_face(const KParams<R>& P, const R Dchi[NP][NM],
-                                        const R dchiL[3][NM], const R dcbL[3][NM],
-                                        const R pb[NP], const R gn[NP], const R gt1[NP],
-                                        const R gt2[NP], const R dph[3], const R mL[NM],
-                                        const R mU[NM], R Phi[NM]) {
+template <typename R, bool ZF, typename KP, typename CP>
+__device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP], const R gn[NP],
+                                        const R gt1[NP], const R gt2[NP], const R dph[3],
+                                        const R mL[NM], const R mU[NM], R Phi[NM]) {
   R M0 = R(0), M1 = R(0);
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
-    M0 += Dchi[a][0] * pb[a];
-    M1 += Dchi[a][1] * pb[a];
+    M0 += (R)(ZF ? C.DchiZ[a][0] : C.Dchi[a][0]) * pb[a];
+    M1 += (R)(ZF ? C.DchiZ[a][1] : C.Dchi[a][1]) * pb[a];
   }
-  Phi[0] = M0 * (mU[0] - mL[0]) * P.inv_dx;
-  Phi[1] = M1 * (mU[1] - mL[1]) * P.inv_dx;
+  Phi[0] = M0 * (mU[0] - mL[0]) * (R)P.inv_dx;
+  Phi[1] = M1 * (mU[1] - mL[1]) * (R)P.inv_dx;
   if (!P.antitrap) return;
   const R mb0 = R(0.5) * (mL[0] + mU[0]), mb1 = R(0.5) * (mL[1] + mU[1]);
   const R gl2 = gn[LQ] * gn[LQ] + gt1[LQ] * gt1[LQ] + gt2[LQ] * gt2[LQ];
   if (!(gl2 > R(0))) return;
   const R pl = pb[LQ];
   const R Sb = pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2] + pl * pl;
-  const R base = pl * rcp_(Sb) * rsq_(gl2) * P.half_inv_dt;
+  const R base = pl * rcp_(Sb) * rsq_(gl2) * (R)P.half_inv_dt;
   R J0 = R(0), J1 = R(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -295,13 +310,17 @@ __device__ __forceinline__ void mu_face(const KParams<R>& P, const R Dchi[NP][NM
     R ga2 = gn[a] * gn[a] + gt1[a] * gt1[a] + gt2[a] * gt2[a];
     if (prod > R(0) && ga2 > R(0)) {
       R dot = gn[a] * gn[LQ] + gt1[a] * gt1[LQ] + gt2[a] * gt2[LQ];
-      R coef = sqrt_(prod) * base * dph[a] * div_(dot * gn[a], ga2);
-      J0 += coef * (dchiL[a][0] * mb0 + dcbL[a][0]);
-      J1 += coef * (dchiL[a][1] * mb1 + dcbL[a][1]);
+      R coef = (prod * rsq_(prod)) * base * dph[a] * (dot * gn[a]) * rcp_(ga2);
+      const R dc0 = (R)(ZF ? C.dchiLZ[a][0] : C.dchiL[a][0]) * mb0 +
+                    (R)(ZF ? C.dcbLZ[a][0] : C.dcbL[a][0]);
+      const R dc1 = (R)(ZF ? C.dchiLZ[a][1] : C.dchiL[a][1]) * mb1 +
+                    (R)(ZF ? C.dcbLZ[a][1] : C.dcbL[a][1]);
+      J0 += coef * dc0;
+      J1 += coef * dc1;
     }
   }
-  Phi[0] -= P.pieps4 * J0;
-  Phi[1] -= P.pieps4 * J1;
+  Phi[0] -= (R)P.pieps4 * J0;
+  Phi[1] -= (R)P.pieps4 * J1;
 }
 
 // ---------------------------------------------------------- mu cell stage
@@ -311,10 +330,9 @@ __device__ __forceinline__ void mu_face(const KParams<R>& P, const R Dchi[NP][NM
 //   src_i = sum_a (h1_a - h0_a)(chi_ai mu_i + cbar_ai - cbar_li)
 //         + sum_a h1_a (dchi_ai mu_i + dcbar_ai)
 //   mu_i^{n+1} = mu_i + (dt div_i - src_i) / sum_a h1_a chi_ai(T^{n+1})
-template <typename R>
-__device__ __forceinline__ void mu_cell(const KParams<R>& P, const PlaneCoef<R>& C,
-                                        const R p0[NP], const R p1[NP], const R mu[NM],
-                                        const R div[NM], R out[NM]) {
+template <typename R, typename KP, typename CP>
+__device__ __forceinline__ void mu_cell(const KP& P, const CP& C, const R p0[NP], const R p1[NP],
+                                        const R mu[NM], const R div[NM], R out[NM]) {
   R S0 = p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2] + p0[3] * p0[3];
   R S1 = p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2] + p1[3] * p1[3];
   R i0 = rcp_(S0), i1 = rcp_(S1);
@@ -326,15 +344,15 @@ __device__ __forceinline__ void mu_cell(const KParams<R>& P, const PlaneCoef<R>&
   }
 #pragma unroll
   for (int q = 0; q < NM; ++q) {
-    const R cref = C.cbar[LQ][q];
+    const R cref = (R)C.cbar[LQ][q];
     R src = R(0), chi = R(0);
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      src += (h1[a] - h0[a]) * (C.chi[a][q] * mu[q] + (C.cbar[a][q] - cref)) +
-             h1[a] * (C.dchi[a][q] * mu[q] + C.dcbar[a][q]);
-      chi += h1[a] * C.chi1[a][q];
+      src += (h1[a] - h0[a]) * ((R)C.chi[a][q] * mu[q] + ((R)C.cbar[a][q] - cref)) +
+             h1[a] * ((R)C.dchi[a][q] * mu[q] + (R)C.dcbar[a][q]);
+      chi += h1[a] * (R)C.chi1[a][q];
     }
-    out[q] = mu[q] + div_(P.dt * div[q] - src, chi);
+    out[q] = mu[q] + ((R)P.dt * div[q] - src) * rcp_(chi);
   }
 }
 

@@ -100,9 +100,9 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
 // components gt1, gt2 (axes in increasing order, skipping D), each the
 // average of the central differences at L and U (4-point stencil).
 template <typename R, int D, bool FULL>
-__device__ __forceinline__ void gather_face(const R* const* f, const Geo& g, int xl, int yl,
-                                            int zl, R inv_dx, R inv_4dx, R pb[NP], R gn[NP],
-                                            R gt1[NP], R gt2[NP]) {
+__device__ __forceinline__ void gather_face(const PF_GLOBAL R* const* f, const Geo& g, int xl,
+                                            int yl, int zl, R inv_dx, R inv_4dx, R pb[NP],
+                                            R gn[NP], R gt1[NP], R gt2[NP]) {
   const int xu = D == 0 ? g.xp(xl) : xl;
   const int yu = D == 1 ? g.yp(yl) : yl;
   const int zu = D == 2 ? zl + 1 : zl;
@@ -115,7 +115,6 @@ __device__ __forceinline__ void gather_face(const R* const* f, const Geo& g, int
     gt1[a] = gt2[a] = R(0);
   }
   if constexpr (FULL) {
-    // tangential axes
     constexpr int t1 = D == 0 ? 1 : 0;
     constexpr int t2 = D == 2 ? 1 : 2;
     int64_t o1[4], o2[4];  // L+, U+, L-, U-
@@ -142,16 +141,17 @@ __device__ __forceinline__ void gather_face(const R* const* f, const Geo& g, int
   }
 }
 
-template <typename R, bool ANISO, int D>
-__device__ __forceinline__ void phi_face_at(const KParams<R>& P, const R* const* f, const Geo& g,
-                                            int xl, int yl, int zl, R F[NP], R S[NP]) {
+template <typename R, bool ANISO, int D, typename KP>
+__device__ __forceinline__ void phi_face_at(const KP& P, const PF_GLOBAL R* const* f,
+                                            const Geo& g, int xl, int yl, int zl, R F[NP],
+                                            R S[NP]) {
   if (D == 2 && (zl < 0 || zl >= g.nz - 1)) {  // zero-flux z boundary
 #pragma unroll
     for (int a = 0; a < NP; ++a) F[a] = S[a] = R(0);
     return;
   }
   R pb[NP], gn[NP], gt1[NP], gt2[NP];
-  gather_face<R, D, ANISO>(f, g, xl, yl, zl, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+  gather_face<R, D, ANISO>(f, g, xl, yl, zl, (R)P.inv_dx, (R)P.inv_4dx, pb, gn, gt1, gt2);
   phi_face<R, ANISO, D>(P, pb, gn, gt1, gt2, F, S);
 }
 
@@ -161,17 +161,18 @@ __global__ __launch_bounds__(kTileThreads) void phi_direct_kernel(DevDomain* con
                                                                   int total) {
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int di = find_domain(first, ndom, item);
-    const DevDomain& d = *doms[di];
+    const PF_CONST DevDomain& d = domain_at(doms, di);
     if (!d.active) continue;
-    const WorkTile w = decode_item(d, item - first[di], threadIdx.x);
+    const WorkTile w = decode_item(d, item - first_item(first, di), threadIdx.x);
     if (!w.valid) continue;
     const Geo g = make_geo(d);
-    const KParams<R>& P = kparams<R>(d);
-    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
-    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
-    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
-    const R* ph[NP] = {src, src + d.fstride, src + 2 * d.fstride, src + 3 * d.fstride};
-    const R* mu[NM] = {src + 4 * d.fstride, src + 5 * d.fstride};
+    const auto& P = kparams<R>(d);
+    const PF_CONST PlaneCoef<R>* tab = to_const(static_cast<const PlaneCoef<R>*>(d.coef));
+    const PF_GLOBAL R* src = to_global(static_cast<const R*>(d.copy[d.cur_src]));
+    PF_GLOBAL R* dst = to_global(static_cast<R*>(d.copy[d.cur_src ^ 1]));
+    const int64_t fs = d.fstride;
+    const PF_GLOBAL R* ph[NP] = {src, src + fs, src + 2 * fs, src + 3 * fs};
+    const PF_GLOBAL R* mu[NM] = {src + 4 * fs, src + 5 * fs};
     const int x = w.x, y = w.y;
     const int xm = g.xm(x), ym = g.ym(y);
     for (int k = w.z0; k < w.z1; ++k) {
@@ -199,22 +200,22 @@ __global__ __launch_bounds__(kTileThreads) void phi_direct_kernel(DevDomain* con
       double out[NP];
       phi_cell<R>(P, tab[k], pc, mc, Ss, Fd, out);
 #pragma unroll
-      for (int a = 0; a < NP; ++a) dst[a * d.fstride + o] = (R)out[a];
+      for (int a = 0; a < NP; ++a) dst[a * fs + o] = (R)out[a];
     }
   }
 }
 
-template <typename R, int D>
-__device__ __forceinline__ void mu_face_at(const KParams<R>& P, const PlaneCoef<R>& C,
-                                           const R* const* f0, const R* const* f1,
-                                           const R* const* mu, const Geo& g, int xl, int yl,
-                                           int zl, R Phi[NM]) {
+template <typename R, int D, typename KP, typename CP>
+__device__ __forceinline__ void mu_face_at(const KP& P, const CP& C, const PF_GLOBAL R* const* f0,
+                                           const PF_GLOBAL R* const* f1,
+                                           const PF_GLOBAL R* const* mu, const Geo& g, int xl,
+                                           int yl, int zl, R Phi[NM]) {
   if (D == 2 && (zl < 0 || zl >= g.nz - 1)) {
     Phi[0] = Phi[1] = R(0);
     return;
   }
   R pb[NP], gn[NP], gt1[NP], gt2[NP];
-  gather_face<R, D, true>(f0, g, xl, yl, zl, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+  gather_face<R, D, true>(f0, g, xl, yl, zl, (R)P.inv_dx, (R)P.inv_4dx, pb, gn, gt1, gt2);
   const int xu = D == 0 ? g.xp(xl) : xl;
   const int yu = D == 1 ? g.yp(yl) : yl;
   const int zu = D == 2 ? zl + 1 : zl;
@@ -224,10 +225,7 @@ __device__ __forceinline__ void mu_face_at(const KParams<R>& P, const PlaneCoef<
   for (int a = 0; a < 3; ++a) dph[a] = (f1[a][oL] - f0[a][oL]) + (f1[a][oU] - f0[a][oU]);
 #pragma unroll
   for (int q = 0; q < NM; ++q) { mL[q] = mu[q][oL]; mU[q] = mu[q][oU]; }
-  if (D == 2)
-    mu_face<R, D>(P, C.DchiZ, C.dchiLZ, C.dcbLZ, pb, gn, gt1, gt2, dph, mL, mU, Phi);
-  else
-    mu_face<R, D>(P, C.Dchi, C.dchiL, C.dcbL, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+  mu_face<R, D == 2>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
 }
 
 template <typename R>
@@ -236,19 +234,20 @@ __global__ __launch_bounds__(kTileThreads) void mu_direct_kernel(DevDomain* cons
                                                                  int total) {
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int di = find_domain(first, ndom, item);
-    const DevDomain& d = *doms[di];
+    const PF_CONST DevDomain& d = domain_at(doms, di);
     if (!d.active) continue;
-    const WorkTile w = decode_item(d, item - first[di], threadIdx.x);
+    const WorkTile w = decode_item(d, item - first_item(first, di), threadIdx.x);
     if (!w.valid) continue;
     const Geo g = make_geo(d);
-    const KParams<R>& P = kparams<R>(d);
-    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
-    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
-    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
-    const R* p0[NP] = {src, src + d.fstride, src + 2 * d.fstride, src + 3 * d.fstride};
-    const R* mu[NM] = {src + 4 * d.fstride, src + 5 * d.fstride};
-    const R* p1[NP] = {dst, dst + d.fstride, dst + 2 * d.fstride, dst + 3 * d.fstride};
-    R* mo[NM] = {dst + 4 * d.fstride, dst + 5 * d.fstride};
+    const auto& P = kparams<R>(d);
+    const PF_CONST PlaneCoef<R>* tab = to_const(static_cast<const PlaneCoef<R>*>(d.coef));
+    const PF_GLOBAL R* src = to_global(static_cast<const R*>(d.copy[d.cur_src]));
+    PF_GLOBAL R* dst = to_global(static_cast<R*>(d.copy[d.cur_src ^ 1]));
+    const int64_t fs = d.fstride;
+    const PF_GLOBAL R* p0[NP] = {src, src + fs, src + 2 * fs, src + 3 * fs};
+    const PF_GLOBAL R* mu[NM] = {src + 4 * fs, src + 5 * fs};
+    const PF_GLOBAL R* p1[NP] = {dst, dst + fs, dst + 2 * fs, dst + 3 * fs};
+    PF_GLOBAL R* mo[NM] = {dst + 4 * fs, dst + 5 * fs};
     const int x = w.x, y = w.y;
     const int xm = g.xm(x), ym = g.ym(y);
     for (int k = w.z0; k < w.z1; ++k) {
@@ -258,8 +257,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_direct_kernel(DevDomain* cons
         mo[1][o] = mu[1][o];
         continue;
       }
-      const PlaneCoef<R>& C = tab[k];
-      const PlaneCoef<R>& Cm = tab[k > 0 ? k - 1 : 0];
+      const auto& C = tab[k];
+      const auto& Cm = tab[k > 0 ? k - 1 : 0];
       R div[NM] = {R(0), R(0)}, Pu[NM], Pl[NM];
       mu_face_at<R, 0>(P, C, p0, p1, mu, g, x, y, k, Pu);
       mu_face_at<R, 0>(P, C, p0, p1, mu, g, xm, y, k, Pl);
@@ -271,8 +270,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_direct_kernel(DevDomain* cons
       div[1] += Pu[1] - Pl[1];
       mu_face_at<R, 2>(P, C, p0, p1, mu, g, x, y, k, Pu);
       mu_face_at<R, 2>(P, Cm, p0, p1, mu, g, x, y, k - 1, Pl);
-      div[0] = (div[0] + (Pu[0] - Pl[0])) * P.inv_dx;
-      div[1] = (div[1] + (Pu[1] - Pl[1])) * P.inv_dx;
+      div[0] = (div[0] + (Pu[0] - Pl[0])) * (R)P.inv_dx;
+      div[1] = (div[1] + (Pu[1] - Pl[1])) * (R)P.inv_dx;
       R c0[NP], c1[NP], mc[NM], out[NM];
 #pragma unroll
       for (int a = 0; a < NP; ++a) { c0[a] = p0[a][o]; c1[a] = p1[a][o]; }

@@ -28,7 +28,8 @@ struct Geo {
   }
 };
 
-__device__ __forceinline__ Geo make_geo(const DevDomain& d) {
+template <typename DD>
+__device__ __forceinline__ Geo make_geo(const DD& d) {
   Geo g;
   g.nx = d.nx;
   g.ny = d.ny;
@@ -39,7 +40,8 @@ __device__ __forceinline__ Geo make_geo(const DevDomain& d) {
 }
 
 // Domain owning flattened work item `item` (binary search of the prefix sums).
-__device__ __forceinline__ int find_domain(const int32_t* first, int ndom, int item) {
+__device__ __forceinline__ int find_domain(const int32_t* first_g, int ndom, int item) {
+  const PF_CONST int32_t* first = to_const(first_g);
   int lo = 0, hi = ndom - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -58,7 +60,8 @@ struct WorkTile {
   bool valid;  // column inside the domain
 };
 
-__device__ __forceinline__ WorkTile decode_item(const DevDomain& d, int local, int tid) {
+template <typename DD>
+__device__ __forceinline__ WorkTile decode_item(const DD& d, int local, int tid) {
   WorkTile w;
   const int ix = local % d.ntx;
   const int r = local / d.ntx;
@@ -74,6 +77,14 @@ __device__ __forceinline__ WorkTile decode_item(const DevDomain& d, int local, i
   w.z1 = min(d.nz, w.z0 + d.zc);
   w.valid = w.x < d.nx && w.y < d.ny;
   return w;
+}
+
+// Descriptor of domain di through the constant address space.
+__device__ __forceinline__ const PF_CONST DevDomain& domain_at(DevDomain* const* doms, int di) {
+  return *to_const(to_const(doms)[di]);
+}
+__device__ __forceinline__ int first_item(const int32_t* first, int di) {
+  return to_const(first)[di];
 }
 
 hipError_t launch_phi_tiled(const struct LaunchSet& L, int prec, bool aniso, hipStream_t s);

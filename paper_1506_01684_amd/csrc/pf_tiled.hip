@@ -15,6 +15,9 @@
 //     direction, so every face rounds identically wherever it is computed;
 //   - the next plane's loads are issued before the face stage and written
 //     to LDS after it, so their latency overlaps the arithmetic.
+// LDS layout avoids bank conflicts: phi is stored as 16-byte vectors
+// (two doubles or four floats per lane access) and face values as
+// structure of arrays (consecutive lanes touch consecutive words).
 #include <hip/hip_runtime.h>
 
 #include "pf_device.h"
@@ -24,13 +27,43 @@
 namespace pfk {
 
 template <typename R>
-struct alignas(4 * sizeof(R)) V4 {
+struct V4 {
   R v[4];
 };
 
 constexpr int kMaxHalo = 400;  // (tx+2)(ty+2): 66*6 = 396, 34*10 = 340
 constexpr int kMaxFx = 264;    // ty (tx+1): 4*65 = 260, 8*33 = 264
 constexpr int kMaxFy = 320;    // (ty+1) tx: 5*64 = 320, 9*32 = 288
+
+// LDS ring of phi planes: NSLOT planes of (tx+2)(ty+2) cells.
+template <typename R, int NSLOT>
+struct LdsPhi;
+
+template <int NSLOT>
+struct LdsPhi<double, NSLOT> {
+  double2 lo[NSLOT][kMaxHalo];  // phi_0, phi_1
+  double2 hi[NSLOT][kMaxHalo];  // phi_2, phi_3
+  __device__ __forceinline__ V4<double> get(int s, int c) const {
+    const double2 a = lo[s][c], b = hi[s][c];
+    return {{a.x, a.y, b.x, b.y}};
+  }
+  __device__ __forceinline__ void put(int s, int c, const V4<double>& v) {
+    lo[s][c] = make_double2(v.v[0], v.v[1]);
+    hi[s][c] = make_double2(v.v[2], v.v[3]);
+  }
+};
+
+template <int NSLOT>
+struct LdsPhi<float, NSLOT> {
+  float4 q[NSLOT][kMaxHalo];
+  __device__ __forceinline__ V4<float> get(int s, int c) const {
+    const float4 a = q[s][c];
+    return {{a.x, a.y, a.z, a.w}};
+  }
+  __device__ __forceinline__ void put(int s, int c, const V4<float>& v) {
+    q[s][c] = make_float4(v.v[0], v.v[1], v.v[2], v.v[3]);
+  }
+};
 
 // Per-item geometry of one thread.
 struct TileGeo {
@@ -48,7 +81,8 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-__device__ __forceinline__ TileGeo make_tile(const DevDomain& d, int local, int t) {
+template <typename DD>
+__device__ __forceinline__ TileGeo make_tile(const DD& d, int local, int t) {
   TileGeo G;
   const WorkTile w = decode_item(d, local, t);
   G.tx = d.tx;
@@ -89,7 +123,7 @@ __device__ __forceinline__ TileGeo make_tile(const DevDomain& d, int local, int 
 }
 
 template <typename R>
-__device__ __forceinline__ V4<R> load4(const R* base, int64_t fstride, int64_t off) {
+__device__ __forceinline__ V4<R> load4(const PF_GLOBAL R* base, int64_t fstride, int64_t off) {
   V4<R> v;
 #pragma unroll
   for (int a = 0; a < NP; ++a) v.v[a] = base[a * fstride + off];
@@ -104,14 +138,14 @@ __device__ __forceinline__ int slot_of(int nslot, int plane) {
 // neighbour along D, planes given by slots (sm, s0, sp) = (k-1, k, k+1) for
 // x/y faces, (s0, sp) = (k, k+1) for z faces.  FULL adds the tangential
 // components (4-point averages of central differences).
-template <typename R, int D, bool FULL>
-__device__ __forceinline__ void lds_face(const V4<R> (*S)[kMaxHalo], const TileGeo& G, int cx,
+template <typename R, int D, bool FULL, int NSLOT>
+__device__ __forceinline__ void lds_face(const LdsPhi<R, NSLOT>& S, const TileGeo& G, int cx,
                                          int cy, int sm, int s0, int sp, R inv_dx, R inv_4dx,
                                          R pb[NP], R gn[NP], R gt1[NP], R gt2[NP]) {
   const int cL = G.ci(cx, cy);
   const int cU = D == 0 ? G.ci(cx + 1, cy) : (D == 1 ? G.ci(cx, cy + 1) : cL);
-  const V4<R> L = S[s0][cL];
-  const V4<R> U = D == 2 ? S[sp][cL] : S[s0][cU];
+  const V4<R> L = S.get(s0, cL);
+  const V4<R> U = D == 2 ? S.get(sp, cL) : S.get(s0, cU);
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
     pb[a] = R(0.5) * (L.v[a] + U.v[a]);
@@ -121,32 +155,32 @@ __device__ __forceinline__ void lds_face(const V4<R> (*S)[kMaxHalo], const TileG
   if constexpr (FULL) {
     V4<R> p1L, p1U, m1L, m1U, p2L, p2U, m2L, m2U;
     if constexpr (D == 0) {  // tangential y (in plane), z (slots)
-      p1L = S[s0][G.ci(cx, cy + 1)];
-      p1U = S[s0][G.ci(cx + 1, cy + 1)];
-      m1L = S[s0][G.ci(cx, cy - 1)];
-      m1U = S[s0][G.ci(cx + 1, cy - 1)];
-      p2L = S[sp][cL];
-      p2U = S[sp][cU];
-      m2L = S[sm][cL];
-      m2U = S[sm][cU];
+      p1L = S.get(s0, G.ci(cx, cy + 1));
+      p1U = S.get(s0, G.ci(cx + 1, cy + 1));
+      m1L = S.get(s0, G.ci(cx, cy - 1));
+      m1U = S.get(s0, G.ci(cx + 1, cy - 1));
+      p2L = S.get(sp, cL);
+      p2U = S.get(sp, cU);
+      m2L = S.get(sm, cL);
+      m2U = S.get(sm, cU);
     } else if constexpr (D == 1) {  // tangential x, z
-      p1L = S[s0][G.ci(cx + 1, cy)];
-      p1U = S[s0][G.ci(cx + 1, cy + 1)];
-      m1L = S[s0][G.ci(cx - 1, cy)];
-      m1U = S[s0][G.ci(cx - 1, cy + 1)];
-      p2L = S[sp][cL];
-      p2U = S[sp][cU];
-      m2L = S[sm][cL];
-      m2U = S[sm][cU];
+      p1L = S.get(s0, G.ci(cx + 1, cy));
+      p1U = S.get(s0, G.ci(cx + 1, cy + 1));
+      m1L = S.get(s0, G.ci(cx - 1, cy));
+      m1U = S.get(s0, G.ci(cx - 1, cy + 1));
+      p2L = S.get(sp, cL);
+      p2U = S.get(sp, cU);
+      m2L = S.get(sm, cL);
+      m2U = S.get(sm, cU);
     } else {  // tangential x, y; L in plane k (s0), U in plane k+1 (sp)
-      p1L = S[s0][G.ci(cx + 1, cy)];
-      p1U = S[sp][G.ci(cx + 1, cy)];
-      m1L = S[s0][G.ci(cx - 1, cy)];
-      m1U = S[sp][G.ci(cx - 1, cy)];
-      p2L = S[s0][G.ci(cx, cy + 1)];
-      p2U = S[sp][G.ci(cx, cy + 1)];
-      m2L = S[s0][G.ci(cx, cy - 1)];
-      m2U = S[sp][G.ci(cx, cy - 1)];
+      p1L = S.get(s0, G.ci(cx + 1, cy));
+      p1U = S.get(sp, G.ci(cx + 1, cy));
+      m1L = S.get(s0, G.ci(cx - 1, cy));
+      m1U = S.get(sp, G.ci(cx - 1, cy));
+      p2L = S.get(s0, G.ci(cx, cy + 1));
+      p2U = S.get(sp, G.ci(cx, cy + 1));
+      m2L = S.get(s0, G.ci(cx, cy - 1));
+      m2U = S.get(sp, G.ci(cx, cy - 1));
     }
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
@@ -154,6 +188,35 @@ __device__ __forceinline__ void lds_face(const V4<R> (*S)[kMaxHalo], const TileG
       gt2[a] = ((p2L.v[a] + p2U.v[a]) - (m2L.v[a] + m2U.v[a])) * inv_4dx;
     }
   }
+}
+
+// Common per-item setup of both sweeps.
+template <typename R>
+struct ItemCtx {
+  const PF_CONST DevDomain* dp;
+  TileGeo G;
+  Geo g;
+  const PF_CONST PlaneCoef<R>* tab;
+  const PF_GLOBAL R* src;
+  PF_GLOBAL R* dst;
+  int64_t fs, plane;
+};
+
+template <typename R>
+__device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t* first,
+                                           int ndom, int item, int t, ItemCtx<R>& X) {
+  const int di = find_domain(first, ndom, item);
+  const PF_CONST DevDomain& d = domain_at(doms, di);
+  if (!d.active) return false;  // uniform over the work group
+  X.dp = &d;
+  X.G = make_tile(d, item - first_item(first, di), t);
+  X.g = make_geo(d);
+  X.tab = to_const(static_cast<const PlaneCoef<R>*>(d.coef));
+  X.src = to_global(static_cast<const R*>(d.copy[d.cur_src]));
+  X.dst = to_global(static_cast<R*>(d.copy[d.cur_src ^ 1]));
+  X.fs = d.fstride;
+  X.plane = d.plane;
+  return true;
 }
 
 // ============================================================ phi-sweep
@@ -164,34 +227,33 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
                                                                  int total) {
   constexpr int NSLOT = ANISO ? 3 : 1;
   constexpr int AHEAD = ANISO ? 2 : 1;  // plane loaded during iteration k: k + AHEAD
-  __shared__ V4<R> s_phi[NSLOT][kMaxHalo];
-  __shared__ R s_fx[kMaxFx][2 * NP];  // F[0..3], S[0..3]
-  __shared__ R s_fy[kMaxFy][2 * NP];
+  __shared__ LdsPhi<R, NSLOT> s_phi;
+  __shared__ R s_fx[2 * NP][kMaxFx];  // F[0..3], S[0..3] of x faces
+  __shared__ R s_fy[2 * NP][kMaxFy];
   const int t = threadIdx.x;
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int di = find_domain(first, ndom, item);
-    const DevDomain& d = *doms[di];
-    if (!d.active) continue;  // uniform over the work group
-    const TileGeo G = make_tile(d, item - first[di], t);
-    const Geo g = make_geo(d);
-    const KParams<R>& P = kparams<R>(d);
-    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
-    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
-    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
-    const R* mu0 = src + 4 * d.fstride;
-    const R* mu1 = src + 5 * d.fstride;
-    const int64_t fs = d.fstride;
+    ItemCtx<R> X;
+    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    const TileGeo& G = X.G;
+    const Geo& g = X.g;
+    const auto& P = kparams<R>(*X.dp);
+    const PF_GLOBAL R* src = X.src;
+    PF_GLOBAL R* dst = X.dst;
+    const int64_t fs = X.fs, pl = X.plane;
+    const PF_GLOBAL R* mu0 = src + 4 * fs;
+    const PF_GLOBAL R* mu1 = src + 5 * fs;
+    const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
     const int kstart = G.z0 - 1;
 
-    // prime the LDS ring with planes kstart-1 .. kstart+AHEAD-1 (NSLOT planes)
+    // prime the LDS ring with planes kstart-1 .. kstart+1 (ANISO) or kstart
     for (int p = kstart - (NSLOT == 3 ? 1 : 0); p <= kstart + (NSLOT == 3 ? 1 : 0); ++p) {
-      const int64_t po = (int64_t)g.zc(p) * d.plane;
+      const int64_t po = (int64_t)g.zc(p) * pl;
       const int sl = slot_of(NSLOT, p);
-      s_phi[sl][G.own_c] = load4(src, fs, po + G.own_off);
-      if (G.halo_c >= 0) s_phi[sl][G.halo_c] = load4(src, fs, po + G.halo_off);
+      s_phi.put(sl, G.own_c, load4(src, fs, po + G.own_off));
+      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4(src, fs, po + G.halo_off));
     }
-    V4<R> own_k = load4(src, fs, (int64_t)g.zc(kstart) * d.plane + G.own_off);
+    V4<R> own_k = load4(src, fs, (int64_t)g.zc(kstart) * pl + G.own_off);
     __syncthreads();
 
     R Fzl[NP], Szl[NP];  // z face below the current plane
@@ -202,13 +264,13 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       const bool cells = k >= G.z0;  // kstart only evaluates the z face above it
       const int sm = slot_of(NSLOT, k - 1), s0 = slot_of(NSLOT, k), sp = slot_of(NSLOT, k + 1);
       // issue the loads of plane k+AHEAD (own column and halo cell)
-      const int64_t pa = (int64_t)g.zc(k + AHEAD) * d.plane;
+      const int64_t pa = (int64_t)g.zc(k + AHEAD) * pl;
       const V4<R> nxt_own = load4(src, fs, pa + G.own_off);
       V4<R> nxt_halo;
       if (G.halo_c >= 0) nxt_halo = load4(src, fs, pa + G.halo_off);
       R mc[NM] = {R(0), R(0)};
       if (cells) {
-        const int64_t o = (int64_t)k * d.plane + G.own_off;
+        const int64_t o = (int64_t)k * pl + G.own_off;
         mc[0] = mu0[o];
         mc[1] = mu1[o];
         // x faces: own upper face, plus the tile's lower edge face for the
@@ -220,12 +282,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
           const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
           R pb[NP], gn[NP], gt1[NP], gt2[NP], F[NP], S[NP];
-          lds_face<R, 0, ANISO>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+          lds_face<R, 0, ANISO>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
           phi_face<R, ANISO, 0>(P, pb, gn, gt1, gt2, F, S);
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
-            s_fx[fo][a] = F[a];
-            s_fx[fo][NP + a] = S[a];
+            s_fx[a][fo] = F[a];
+            s_fx[NP + a][fo] = S[a];
           }
         }
 #pragma unroll 1
@@ -235,12 +297,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
           const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
           R pb[NP], gn[NP], gt1[NP], gt2[NP], F[NP], S[NP];
-          lds_face<R, 1, ANISO>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
+          lds_face<R, 1, ANISO>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
           phi_face<R, ANISO, 1>(P, pb, gn, gt1, gt2, F, S);
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
-            s_fy[fo][a] = F[a];
-            s_fy[fo][NP + a] = S[a];
+            s_fy[a][fo] = F[a];
+            s_fy[NP + a][fo] = S[a];
           }
         }
       }
@@ -252,47 +314,46 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       } else {
         R pb[NP], gn[NP], gt1[NP], gt2[NP];
         if constexpr (ANISO) {
-          lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, P.inv_dx, P.inv_4dx, pb,
-                               gn, gt1, gt2);
+          lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_dx, inv_4dx, pb, gn,
+                               gt1, gt2);
         } else {
           // own column at k (registers) and k+1 (just loaded)
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
             pb[a] = R(0.5) * (own_k.v[a] + nxt_own.v[a]);
-            gn[a] = (nxt_own.v[a] - own_k.v[a]) * P.inv_dx;
+            gn[a] = (nxt_own.v[a] - own_k.v[a]) * inv_dx;
             gt1[a] = gt2[a] = R(0);
           }
         }
         phi_face<R, ANISO, 2>(P, pb, gn, gt1, gt2, Fzu, Szu);
       }
+      V4<R> ownv;
+      if constexpr (ANISO) ownv = s_phi.get(s0, G.own_c);
+      else ownv = own_k;
       __syncthreads();  // B1: faces visible; LDS plane slots of k-1 (or k) free
       {
         const int sl = slot_of(NSLOT, k + AHEAD);
-        s_phi[sl][G.own_c] = nxt_own;
-        if (G.halo_c >= 0) s_phi[sl][G.halo_c] = nxt_halo;
+        s_phi.put(sl, G.own_c, nxt_own);
+        if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, nxt_halo);
       }
       if (cells && G.valid) {
         const int fl = G.ly * (G.tx + 1) + G.lx;  // lower x face; upper is fl+1
         const int yl = G.ly * G.tx + G.lx;        // lower y face; upper is yl+tx
-        R Ss[NP], Fd[NP], pc[NP];
-        V4<R> ownv;
-        if constexpr (ANISO) ownv = s_phi[s0][G.own_c];
-        else ownv = own_k;
+        R Ss[NP], Fd[NP];
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
-          pc[a] = ownv.v[a];
           Ss[a] = R(0);
           Fd[a] = R(0);
-          Ss[a] += s_fx[fl + 1][NP + a] + s_fx[fl][NP + a];
-          Fd[a] += s_fx[fl + 1][a] - s_fx[fl][a];
-          Ss[a] += s_fy[yl + G.tx][NP + a] + s_fy[yl][NP + a];
-          Fd[a] += s_fy[yl + G.tx][a] - s_fy[yl][a];
+          Ss[a] += s_fx[NP + a][fl + 1] + s_fx[NP + a][fl];
+          Fd[a] += s_fx[a][fl + 1] - s_fx[a][fl];
+          Ss[a] += s_fy[NP + a][yl + G.tx] + s_fy[NP + a][yl];
+          Fd[a] += s_fy[a][yl + G.tx] - s_fy[a][yl];
           Ss[a] += Szu[a] + Szl[a];
           Fd[a] += Fzu[a] - Fzl[a];
         }
         double out[NP];
-        phi_cell<R>(P, tab[k], pc, mc, Ss, Fd, out);
-        const int64_t o = (int64_t)k * d.plane + G.own_off;
+        phi_cell<R>(P, X.tab[k], ownv.v, mc, Ss, Fd, out);
+        const int64_t o = (int64_t)k * pl + G.own_off;
 #pragma unroll
         for (int a = 0; a < NP; ++a) dst[a * fs + o] = (R)out[a];
       }
@@ -314,33 +375,32 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
                                                                 const int32_t* first, int ndom,
                                                                 int total) {
   constexpr int NSLOT = 3, AHEAD = 2;
-  __shared__ V4<R> s_phi[NSLOT][kMaxHalo];
-  __shared__ R s_fx[kMaxFx][NM];
-  __shared__ R s_fy[kMaxFy][NM];
+  __shared__ LdsPhi<R, NSLOT> s_phi;
+  __shared__ R s_fx[NM][kMaxFx];
+  __shared__ R s_fy[NM][kMaxFy];
   const int t = threadIdx.x;
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int di = find_domain(first, ndom, item);
-    const DevDomain& d = *doms[di];
-    if (!d.active) continue;
-    const TileGeo G = make_tile(d, item - first[di], t);
-    const Geo g = make_geo(d);
-    const KParams<R>& P = kparams<R>(d);
-    const PlaneCoef<R>* tab = static_cast<const PlaneCoef<R>*>(d.coef);
-    const R* src = static_cast<const R*>(d.copy[d.cur_src]);
-    R* dst = static_cast<R*>(d.copy[d.cur_src ^ 1]);
-    const int64_t fs = d.fstride;
-    const R* p1 = dst;  // phi^{n+1}, written by the phi-sweep
-    const R* mu0 = src + 4 * fs;
-    const R* mu1 = src + 5 * fs;
-    R* mo0 = dst + 4 * fs;
-    R* mo1 = dst + 5 * fs;
+    ItemCtx<R> X;
+    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    const TileGeo& G = X.G;
+    const Geo& g = X.g;
+    const auto& P = kparams<R>(*X.dp);
+    const PF_GLOBAL R* src = X.src;
+    PF_GLOBAL R* dst = X.dst;
+    const int64_t fs = X.fs, pl = X.plane;
+    const PF_GLOBAL R* p1 = dst;  // phi^{n+1}, written by the phi-sweep
+    const PF_GLOBAL R* mu0 = src + 4 * fs;
+    const PF_GLOBAL R* mu1 = src + 5 * fs;
+    PF_GLOBAL R* mo0 = dst + 4 * fs;
+    PF_GLOBAL R* mo1 = dst + 5 * fs;
+    const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
     const int kstart = G.z0 - 1;
 
     if (P.mu_frozen) {  // mu^{n+1} = mu^n (tests of the phi part only)
       if (G.valid)
         for (int k = G.z0; k < G.z1; ++k) {
-          const int64_t o = (int64_t)k * d.plane + G.own_off;
+          const int64_t o = (int64_t)k * pl + G.own_off;
           mo0[o] = mu0[o];
           mo1[o] = mu1[o];
         }
@@ -350,28 +410,28 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
     // in-plane offsets of the face partners (x+1 / y+1 of the own column;
     // the tile's lower-edge faces use x0-1 / y0-1)
     const int gx = G.x0 + G.lx, gy = G.y0 + G.ly;
-    const int64_t off_xu = G.valid ? (int64_t)gy * d.pitch + g.xp(gx) : G.own_off;
-    const int64_t off_yu = G.valid ? (int64_t)g.yp(gy) * d.pitch + gx : G.own_off;
+    const int64_t off_xu = G.valid ? (int64_t)gy * g.pitch + g.xp(gx) : G.own_off;
+    const int64_t off_yu = G.valid ? (int64_t)g.yp(gy) * g.pitch + gx : G.own_off;
     int64_t edge_xL = 0, edge_xU = 0, edge_yL = 0, edge_yU = 0;
     const bool ex = t < G.ty && G.y0 + t < g.ny;
     const bool ey = t < G.tx && G.x0 + t < g.nx;
     if (ex) {
-      edge_xL = (int64_t)(G.y0 + t) * d.pitch + g.xm(G.x0);
-      edge_xU = (int64_t)(G.y0 + t) * d.pitch + G.x0;
+      edge_xL = (int64_t)(G.y0 + t) * g.pitch + g.xm(G.x0);
+      edge_xU = (int64_t)(G.y0 + t) * g.pitch + G.x0;
     }
     if (ey) {
-      edge_yL = (int64_t)g.ym(G.y0) * d.pitch + G.x0 + t;
-      edge_yU = (int64_t)G.y0 * d.pitch + G.x0 + t;
+      edge_yL = (int64_t)g.ym(G.y0) * g.pitch + G.x0 + t;
+      edge_yU = (int64_t)G.y0 * g.pitch + G.x0 + t;
     }
 
     for (int p = kstart - 1; p <= kstart + 1; ++p) {
-      const int64_t po = (int64_t)g.zc(p) * d.plane;
+      const int64_t po = (int64_t)g.zc(p) * pl;
       const int sl = slot_of(NSLOT, p);
-      s_phi[sl][G.own_c] = load4(src, fs, po + G.own_off);
-      if (G.halo_c >= 0) s_phi[sl][G.halo_c] = load4(src, fs, po + G.halo_off);
+      s_phi.put(sl, G.own_c, load4(src, fs, po + G.own_off));
+      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4(src, fs, po + G.halo_off));
     }
     // phi^{n+1} and mu^n of the own column at plane kstart
-    int64_t ok = (int64_t)g.zc(kstart) * d.plane + G.own_off;
+    const int64_t ok = (int64_t)g.zc(kstart) * pl + G.own_off;
     V4<R> own1 = load4(p1, fs, ok);
     R ownm[NM] = {mu0[ok], mu1[ok]};
     __syncthreads();
@@ -380,16 +440,16 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
     for (int k = kstart; k < G.z1; ++k) {
       const bool cells = k >= G.z0;
       const int sm = slot_of(NSLOT, k - 1), s0 = slot_of(NSLOT, k), sp = slot_of(NSLOT, k + 1);
-      const int64_t pa = (int64_t)g.zc(k + AHEAD) * d.plane;
+      const int64_t pa = (int64_t)g.zc(k + AHEAD) * pl;
       const V4<R> nxt_own = load4(src, fs, pa + G.own_off);
       V4<R> nxt_halo;
       if (G.halo_c >= 0) nxt_halo = load4(src, fs, pa + G.halo_off);
       // own column at k+1: phi^{n+1}, mu^n (for the z face above k)
-      const int64_t o1 = (int64_t)g.zp(k) * d.plane + G.own_off;
+      const int64_t o1 = (int64_t)g.zp(k) * pl + G.own_off;
       const V4<R> up1 = load4(p1, fs, o1);
       const R upm[NM] = {mu0[o1], mu1[o1]};
-      const int64_t pk = (int64_t)(k < 0 ? 0 : k) * d.plane;
-      const PlaneCoef<R>& C = tab[k < 0 ? 0 : k];
+      const int64_t pk = (int64_t)(k < 0 ? 0 : k) * pl;
+      const auto& C = X.tab[k < 0 ? 0 : k];
       if (cells) {
 #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
@@ -400,8 +460,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           const int64_t oL = pk + (edge ? edge_xL : G.own_off);
           const int64_t oU = pk + (edge ? edge_xU : off_xu);
           R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3], mL[NM], mU[NM], Phi[NM];
-          lds_face<R, 0, true>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
-          const V4<R> L0 = s_phi[s0][G.ci(cx, cy)], U0 = s_phi[s0][G.ci(cx + 1, cy)];
+          lds_face<R, 0, true>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
+          const V4<R> L0 = s_phi.get(s0, G.ci(cx, cy)), U0 = s_phi.get(s0, G.ci(cx + 1, cy));
 #pragma unroll
           for (int a = 0; a < 3; ++a)
             dph[a] = (p1[a * fs + oL] - L0.v[a]) + (p1[a * fs + oU] - U0.v[a]);
@@ -409,9 +469,9 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           mL[1] = mu1[oL];
           mU[0] = mu0[oU];
           mU[1] = mu1[oU];
-          mu_face<R, 0>(P, C.Dchi, C.dchiL, C.dcbL, pb, gn, gt1, gt2, dph, mL, mU, Phi);
-          s_fx[fo][0] = Phi[0];
-          s_fx[fo][1] = Phi[1];
+          mu_face<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          s_fx[0][fo] = Phi[0];
+          s_fx[1][fo] = Phi[1];
         }
 #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
@@ -422,8 +482,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           const int64_t oL = pk + (edge ? edge_yL : G.own_off);
           const int64_t oU = pk + (edge ? edge_yU : off_yu);
           R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3], mL[NM], mU[NM], Phi[NM];
-          lds_face<R, 1, true>(s_phi, G, cx, cy, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn, gt1, gt2);
-          const V4<R> L0 = s_phi[s0][G.ci(cx, cy)], U0 = s_phi[s0][G.ci(cx, cy + 1)];
+          lds_face<R, 1, true>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
+          const V4<R> L0 = s_phi.get(s0, G.ci(cx, cy)), U0 = s_phi.get(s0, G.ci(cx, cy + 1));
 #pragma unroll
           for (int a = 0; a < 3; ++a)
             dph[a] = (p1[a * fs + oL] - L0.v[a]) + (p1[a * fs + oU] - U0.v[a]);
@@ -431,29 +491,29 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           mL[1] = mu1[oL];
           mU[0] = mu0[oU];
           mU[1] = mu1[oU];
-          mu_face<R, 1>(P, C.Dchi, C.dchiL, C.dcbL, pb, gn, gt1, gt2, dph, mL, mU, Phi);
-          s_fy[fo][0] = Phi[0];
-          s_fy[fo][1] = Phi[1];
+          mu_face<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          s_fy[0][fo] = Phi[0];
+          s_fy[1][fo] = Phi[1];
         }
       }
       // z face above plane k
       R Pzu[NM] = {R(0), R(0)};
       if (k >= 0 && k < g.nz - 1) {
         R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3];
-        lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, P.inv_dx, P.inv_4dx, pb, gn,
+        lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_dx, inv_4dx, pb, gn,
                              gt1, gt2);
-        const V4<R> L0 = s_phi[s0][G.own_c], U0 = s_phi[sp][G.own_c];
+        const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
 #pragma unroll
         for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
-        mu_face<R, 2>(P, C.DchiZ, C.dchiLZ, C.dcbLZ, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+        mu_face<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
       }
       V4<R> own0;
-      if (cells) own0 = s_phi[s0][G.own_c];
+      if (cells) own0 = s_phi.get(s0, G.own_c);
       __syncthreads();  // B1
       {
         const int sl = slot_of(NSLOT, k + AHEAD);
-        s_phi[sl][G.own_c] = nxt_own;
-        if (G.halo_c >= 0) s_phi[sl][G.halo_c] = nxt_halo;
+        s_phi.put(sl, G.own_c, nxt_own);
+        if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, nxt_halo);
       }
       if (cells && G.valid) {
         const int fl = G.ly * (G.tx + 1) + G.lx;
@@ -462,12 +522,12 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
 #pragma unroll
         for (int q = 0; q < NM; ++q) {
           div[q] = R(0);
-          div[q] += s_fx[fl + 1][q] - s_fx[fl][q];
-          div[q] += s_fy[yl + G.tx][q] - s_fy[yl][q];
-          div[q] = (div[q] + (Pzu[q] - Pzl[q])) * P.inv_dx;
+          div[q] += s_fx[q][fl + 1] - s_fx[q][fl];
+          div[q] += s_fy[q][yl + G.tx] - s_fy[q][yl];
+          div[q] = (div[q] + (Pzu[q] - Pzl[q])) * inv_dx;
         }
         mu_cell<R>(P, C, own0.v, own1.v, ownm, div, out);
-        const int64_t o = (int64_t)k * d.plane + G.own_off;
+        const int64_t o = (int64_t)k * pl + G.own_off;
         mo0[o] = out[0];
         mo1[o] = out[1];
       }
