@@ -167,6 +167,7 @@ struct pf_domain {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> timing_events;
   pf_pack* pack = nullptr;
+  hipStream_t pack_stream = nullptr;  // stream of the pack this domain belongs to
 
   char* fields(int copy) const { return base + L.off_fields + (size_t)copy * L.copy_bytes; }
   double* partials() const { return reinterpret_cast<double*>(base + L.off_partials); }
@@ -189,8 +190,17 @@ pf_status upload_desc(pf_domain* d) {
   return PF_OK;
 }
 
+// Wait for the domain's own stream and, for a pack member, the pack's.
+pf_status sync_domain(pf_domain* d) {
+  PF_HIP(hipStreamSynchronize(d->stream));
+  if (d->pack) PF_HIP(hipStreamSynchronize(d->pack_stream));
+  return PF_OK;
+}
+
 // Read the device descriptor's dynamic state (step, parity, steps left).
 pf_status fetch_state(pf_domain* d, DevDomain& out) {
+  pf_status st = sync_domain(d);
+  if (st != PF_OK) return st;
   PF_HIP(hipMemcpyAsync(&out, d->dev, sizeof(DevDomain), hipMemcpyDeviceToHost, d->stream));
   PF_HIP(hipStreamSynchronize(d->stream));
   return PF_OK;
@@ -570,7 +580,8 @@ pf_status pf_step_timed(pf_domain* d, int64_t n, double* phi_ms, double* mu_ms) 
 
 pf_status pf_sync(pf_domain* d) {
   if (!d) return fail(PF_ERR_INVALID_ARG, "null domain");
-  PF_HIP(hipStreamSynchronize(d->stream));
+  pf_status sst = sync_domain(d);
+  if (sst != PF_OK) return sst;
   if (d->diag_pending) {
     double v[kDiagValues];
     PF_HIP(hipMemcpy(v, d->diag_out(), sizeof(v), hipMemcpyDeviceToHost));
@@ -594,7 +605,6 @@ pf_status pf_get_step(const pf_domain* d, int64_t* step) {
 pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
   pf_status st = check_state(d);
   if (st != PF_OK) return st;
-  PF_HIP(hipStreamSynchronize(d->stream));
   DevDomain cur;
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
   const pf_domain_desc& g = d->desc;
@@ -641,6 +651,7 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
 
 void pf_destroy(pf_domain* d) {
   if (!d) return;
+  if (d->pack) (void)pf_pack_remove(d->pack, d);  // never leave a dangling member
   (void)hipStreamSynchronize(d->stream);
   for (auto& e : d->ev)
     if (e) (void)hipEventDestroy(e);
@@ -665,6 +676,7 @@ struct pf_pack {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
+  bool own_stream = false;  // created here because the caller passed NULL
 };
 
 namespace {
@@ -731,11 +743,19 @@ pf_status pf_pack_create(int32_t prec, void* stream, int32_t max_domains, pf_pac
   pk->prec = prec;
   pk->stream = static_cast<hipStream_t>(stream);
   pk->max_domains = max_domains;
+  if (!pk->stream) {  // graphs cannot be captured on the null stream
+    if (hipStreamCreate(&pk->stream) != hipSuccess) {
+      delete pk;
+      return fail(PF_ERR_DEVICE, "pack stream creation failed");
+    }
+    pk->own_stream = true;
+  }
   void* p = nullptr;
   const size_t bytes = align_up(sizeof(DevDomain*) * max_domains, kAlign) +
                        sizeof(int32_t) * (max_domains + 1);
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
+    if (pk->own_stream) (void)hipStreamDestroy(pk->stream);
     delete pk;
     return fail(PF_ERR_OOM, "pack table allocation failed");
   }
@@ -760,6 +780,7 @@ pf_status pf_pack_add(pf_pack* pk, pf_domain* d, int64_t nsteps) {
                    sizeof(nsteps), hipMemcpyHostToDevice));
   pk->members.push_back(d);
   d->pack = pk;
+  d->pack_stream = pk->stream;
   pk->dirty = true;
   return PF_OK;
 }
@@ -774,6 +795,7 @@ pf_status pf_pack_remove(pf_pack* pk, pf_domain* d) {
                    sizeof(unlimited), hipMemcpyHostToDevice));
   pk->members.erase(it);
   d->pack = nullptr;
+  d->pack_stream = nullptr;
   pk->dirty = true;
   return PF_OK;
 }
@@ -816,9 +838,13 @@ pf_status pf_pack_sync(pf_pack* pk) {
 void pf_pack_destroy(pf_pack* pk) {
   if (!pk) return;
   (void)hipStreamSynchronize(pk->stream);
-  for (pf_domain* d : pk->members) d->pack = nullptr;
+  for (pf_domain* d : pk->members) {
+    d->pack = nullptr;
+    d->pack_stream = nullptr;
+  }
   drop_graph(pk);
   if (pk->dev_ptrs) (void)hipFree(pk->dev_ptrs);
+  if (pk->own_stream) (void)hipStreamDestroy(pk->stream);
   delete pk;
 }
 
