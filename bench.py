@@ -77,6 +77,88 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int) -> dict:
     return out
 
 
+def run_pack(count: int, steps: int, warmup: int) -> dict:
+    """64 uneven FP32 domains: one pack (one launch per kernel per step over
+    all domains, step captured in a HIP graph) vs looping single-domain
+    launches over the same domains."""
+    import torch
+
+    import paper_1506_01684_amd as pf
+    import pfinputs
+
+    ws = pfinputs.pack_workloads(count)
+    cells = sum(w["shape"][0] * w["shape"][1] * w["shape"][2] for w in ws)
+
+    def make():
+        doms = []
+        for w in ws:
+            d = pf.Domain(w["shape"], w["prec"])
+            d.set_params(w["params"])
+            d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
+            doms.append(d)
+        return doms
+
+    doms = make()
+    pk = pf.Pack("fp32", max_domains=count)
+    for d in doms:
+        pk.add(d, warmup + steps)
+    pk.step(warmup)
+    pk.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk.step(steps)
+    pk.sync()
+    t_pack = time.perf_counter() - t0
+    pk.close()
+    for d in doms:
+        d.close()
+    doms = make()
+    for d in doms:
+        d.step(warmup)
+    for d in doms:
+        d.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for d in doms:
+            d.step(1)
+    for d in doms:
+        d.sync()
+    t_loop = time.perf_counter() - t0
+    for d in doms:
+        d.close()
+    return {
+        "workload": f"{count} FP32 domains, lateral 32-192, height 64-384, {cells} cells",
+        "steps": steps, "pack_mlups": round(cells * steps / t_pack / 1e6, 1),
+        "loop_mlups": round(cells * steps / t_loop / 1e6, 1),
+        "speedup": round(t_loop / t_pack, 3),
+    }
+
+
+def run_serving(count: int, lateral, steps_rng, rate: float, budget: float, serial: bool) -> dict:
+    """Poisson arrivals of Voronoi solves of mixed size, step count and
+    precision through the continuous-batching server; the serial baseline
+    runs the same trace first come, first served with single-domain
+    launches."""
+    import pfinputs
+    from paper_1506_01684_amd import serving as S
+
+    trace = pfinputs.serving_trace(count=count, rate=rate, lateral=lateral, steps=steps_rng)
+    reqs = [S.request_from_trace(t) for t in trace]
+    be = S.GpuBackend(max_domains=256)
+    srv = S.Server(be, budget_bytes=budget, max_slots=256, round_steps=25)
+    res = srv.run(reqs)
+    be.shutdown()
+    out = {
+        "workload": f"{count} requests, Poisson {rate}/s, lateral {lateral[0]}-{lateral[1]}, "
+                    f"Nz = 2L, steps {steps_rng[0]}-{steps_rng[1]}, fp32/fp64 half each, "
+                    f"budget {budget / 1e9:.0f} GB",
+        "server": S.summarize(res),
+    }
+    if serial:
+        out["serial_fifo"] = S.summarize(S.run_serial_gpu(reqs))
+    return out
+
+
 def run_cpu_baseline(workload: str, budget_s: float = 20.0) -> dict:
     """The FP64 oracle (as it stands) on the host's cores, on a bounded sample:
     full steps of the headline domain from its Voronoi initial state."""
@@ -114,6 +196,13 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-pack", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--pack-steps", type=int, default=100)
+    ap.add_argument("--serve-count", type=int, default=64)
+    ap.add_argument("--full-serving", action="store_true",
+                    help="only run the full serving trace: 128 requests, lateral 64-384, "
+                         "steps 200-5000, 200 GB budget (long)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times "
                          "(reference for the FETCH_SIZE/WRITE_SIZE counter scale)")
@@ -127,6 +216,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.calibrate_copy, "repeats": 5}))
+        return
+    if args.full_serving:
+        r = run_serving(128, (64, 384), (200, 5000), 20.0, 200e9, serial=False)
+        print(json.dumps({"metric": "served-solve latency (p50/p99)", "serving": r}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -174,6 +267,13 @@ def main():
             "phi_sweep_gbs": round(r32["phi_gbs"], 1), "mu_sweep_gbs": round(r32["mu_gbs"], 1),
             "steps": args.fp32_steps,
         }
+    if not args.no_pack and args.workload == "c2":
+        _log("[bench] pack of 64 domains")
+        line["pack"] = run_pack(64, args.pack_steps, 5)
+    if not args.no_serve and args.workload == "c2":
+        _log("[bench] serving trace")
+        line["serving"] = run_serving(args.serve_count, (64, 160), (200, 1000), 20.0, 200e9,
+                                      serial=True)
     if not args.no_cpu:
         _log("[bench] timing the CPU oracle")
         line["cpu_baseline"] = run_cpu_baseline(args.workload)

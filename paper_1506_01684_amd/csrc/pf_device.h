@@ -85,6 +85,7 @@ struct DevDomain {
   int64_t plane, fstride;     // plane stride; field stride (elements)
   int32_t tx, ty, zc;         // tile: tx * ty threads, zc planes per item
   int32_t ntx, nty, nzc;      // tiles per axis
+  int32_t xmode, rs;          // XCD y-slab order (1) with rs tile rows per XCD, or plain (0)
   int32_t prec;               // 0 = FP64, 1 = FP32
   int32_t active;             // set by the prologue for the current step
   int64_t step;               // index n of the next step (state time n dt)

@@ -53,20 +53,51 @@ __device__ __forceinline__ int find_domain(const int32_t* first_g, int ndom, int
 
 // One work item: an x-y tile of tx * ty columns and a chunk of zc planes.
 struct WorkTile {
-  int x0, y0;  // tile origin
-  int lx, ly;  // this thread's column inside the tile
-  int x, y;    // this thread's column in the domain
-  int z0, z1;  // planes [z0, z1)
-  bool valid;  // column inside the domain
+  int x0, y0;    // tile origin
+  int lx, ly;    // this thread's column inside the tile
+  int x, y;      // this thread's column in the domain
+  int z0, z1;    // planes [z0, z1)
+  bool item_ok;  // the block has an item (false for padding blocks)
+  bool valid;    // item present and column inside the domain
 };
 
+constexpr int kXcds = 8;
+
+// Block lb (relative to the domain's first block, a multiple of 8) -> tile.
+// Work groups are dispatched round-robin over the 8 XCDs, each with its own
+// L2, so block lb runs on XCD lb % 8.  In y-slab order (xmode = 1) XCD j
+// owns tile rows [j rs, (j+1) rs) over the whole height and walks them x
+// fastest, then y, then z: tiles that read each other's halo cells share one
+// L2, and every XCD gets the same share of the costly interface planes.
+// Plain order (xmode = 0) is x fastest, then y, then z chunk.  Both orders
+// leave padding blocks without an item.
 template <typename DD>
-__device__ __forceinline__ WorkTile decode_item(const DD& d, int local, int tid) {
+__device__ __forceinline__ WorkTile decode_item(const DD& d, int lb, int tid) {
   WorkTile w;
-  const int ix = local % d.ntx;
-  const int r = local / d.ntx;
-  const int iy = r % d.nty;
-  const int iz = r / d.nty;
+  int ix = 0, iy = 0, iz = 0;
+  bool ok;
+  if (d.xmode) {
+    const int j = lb % kXcds, p = lb / kXcds;
+    const int y_lo = j * d.rs;
+    const int rows = min(d.rs, d.nty - y_lo);
+    ok = rows > 0;
+    if (ok) {
+      const int per_z = rows * d.ntx;
+      iz = p / per_z;
+      const int rem = p - iz * per_z;
+      iy = y_lo + rem / d.ntx;
+      ix = rem % d.ntx;
+      ok = iz < d.nzc;
+    }
+  } else {
+    ix = lb % d.ntx;
+    const int r = lb / d.ntx;
+    iy = r % d.nty;
+    iz = r / d.nty;
+    ok = iz < d.nzc;
+  }
+  if (!ok) iz = d.nzc;  // empty plane range
+  w.item_ok = ok;
   w.lx = tid % d.tx;
   w.ly = tid / d.tx;
   w.x0 = ix * d.tx;
@@ -75,7 +106,7 @@ __device__ __forceinline__ WorkTile decode_item(const DD& d, int local, int tid)
   w.y = w.y0 + w.ly;
   w.z0 = iz * d.zc;
   w.z1 = min(d.nz, w.z0 + d.zc);
-  w.valid = w.x < d.nx && w.y < d.ny;
+  w.valid = ok && w.x < d.nx && w.y < d.ny;
   return w;
 }
 

@@ -93,6 +93,13 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
 
 struct Tiling {
   int32_t tx, ty, zc, ntx, nty, nzc;
+  int32_t xmode, rs;  // XCD y-slab order and tile rows per XCD
+  // blocks of one launch over this domain: a multiple of 8 so that a
+  // domain's first block sits on XCD 0 in a pack as well
+  int32_t blocks() const {
+    if (xmode) return 8 * rs * ntx * nzc;
+    return (ntx * nty * nzc + 7) / 8 * 8;
+  }
 };
 
 Tiling choose_tiling(int nx, int ny, int nz) {
@@ -106,6 +113,9 @@ Tiling choose_tiling(int nx, int ny, int nz) {
   zc = std::max<int64_t>(8, std::min<int64_t>(256, zc));
   t.zc = (int32_t)std::min<int64_t>(zc, nz);
   t.nzc = (nz + t.zc - 1) / t.zc;
+  // y-slab order when it leaves at most 1/8 of the blocks without a tile
+  t.rs = (t.nty + 7) / 8;
+  t.xmode = (8 * t.rs - t.nty) * 8 <= 8 * t.rs ? 1 : 0;
   return t;
 }
 
@@ -177,7 +187,7 @@ struct pf_domain {
     s.doms = dev_ptrs;
     s.first = dev_first;
     s.ndom = 1;
-    s.total = T.ntx * T.nty * T.nzc;
+    s.total = T.blocks();
     s.max_nz = desc.nz;
     return s;
   }
@@ -378,13 +388,15 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
   h.ntx = d->T.ntx;
   h.nty = d->T.nty;
   h.nzc = d->T.nzc;
+  h.xmode = d->T.xmode;
+  h.rs = d->T.rs;
   h.prec = desc->prec;
   h.steps_left = -1;
   h.copy[0] = d->fields(0);
   h.copy[1] = d->fields(1);
   h.coef = d->base + L.off_coef;
   h.dx = desc->dx;
-  int32_t first[2] = {0, d->T.ntx * d->T.nty * d->T.nzc};
+  int32_t first[2] = {0, d->T.blocks()};
   DevDomain* self = d->dev;
   pf_status st = PF_OK;
   if (hipMemcpyAsync(d->dev_ptrs, &self, sizeof(self), hipMemcpyHostToDevice, d->stream) !=
@@ -695,7 +707,7 @@ pf_status rebuild_pack(pf_pack* pk) {
   pk->max_nz = 0;
   for (pf_domain* d : pk->members) {
     ptrs.push_back(d->dev);
-    first.push_back(first.back() + d->T.ntx * d->T.nty * d->T.nzc);
+    first.push_back(first.back() + d->T.blocks());
     pk->any_aniso |= d->aniso;
     pk->max_nz = std::max(pk->max_nz, d->desc.nz);
   }

@@ -68,7 +68,7 @@ struct LdsPhi<float, NSLOT> {
 // Per-item geometry of one thread.
 struct TileGeo {
   int tx, ty, lx, ly, x0, y0, z0, z1;
-  bool valid;
+  bool item_ok, valid;
   int own_c;        // LDS index of the own column
   int64_t own_off;  // in-plane offset of the own column (wrapped for idle threads)
   int halo_c;       // LDS index of the halo cell this thread loads (-1: none)
@@ -93,6 +93,7 @@ __device__ __forceinline__ TileGeo make_tile(const DD& d, int local, int t) {
   G.y0 = w.y0;
   G.z0 = w.z0;
   G.z1 = w.z1;
+  G.item_ok = w.item_ok;
   G.valid = w.valid;
   G.own_c = G.ci(w.lx + 1, w.ly + 1);
   const int gx = wrap_mod(w.x, d.nx), gy = wrap_mod(w.y, d.ny);
@@ -210,6 +211,7 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   if (!d.active) return false;  // uniform over the work group
   X.dp = &d;
   X.G = make_tile(d, item - first_item(first, di), t);
+  if (!X.G.item_ok) return false;  // padding block (uniform)
   X.g = make_geo(d);
   X.tab = to_const(static_cast<const PlaneCoef<R>*>(d.coef));
   X.src = to_global(static_cast<const R*>(d.copy[d.cur_src]));
