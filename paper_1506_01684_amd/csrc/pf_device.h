@@ -285,10 +285,10 @@ __device__ __forceinline__ void phi_cell(const KP& P, const CP& C, const R ph[NP
 // pb: face average of phi^n; gn/gt1/gt2: normal and tangential face
 // gradient of phi^n; dph: (phi^{n+1}-phi^n)_L + (...)_U per solid phase;
 // mL/mU: mu^n at the face cells.
+// Diffusive part M_i (mu_i,U - mu_i,L)/dx of the face flux.
 template <typename R, bool ZF, typename KP, typename CP>
-__device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP], const R gn[NP],
-                                        const R gt1[NP], const R gt2[NP], const R dph[3],
-                                        const R mL[NM], const R mU[NM], R Phi[NM]) {
+__device__ __forceinline__ void mu_face_diff(const KP& P, const CP& C, const R pb[NP],
+                                             const R mL[NM], const R mU[NM], R Phi[NM]) {
   R M0 = R(0), M1 = R(0);
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
@@ -297,7 +297,20 @@ __device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP]
   }
   Phi[0] = M0 * (mU[0] - mL[0]) * (R)P.inv_dx;
   Phi[1] = M1 * (mU[1] - mL[1]) * (R)P.inv_dx;
-  if (!P.antitrap) return;
+}
+
+// The anti-trapping current vanishes exactly unless some solid phase and the
+// liquid are both present on the face (w_a = 0 when pb_a pb_l <= 0).
+template <typename R>
+__device__ __forceinline__ bool mu_face_needs_j(const R pb[NP]) {
+  return pb[0] * pb[LQ] > R(0) || pb[1] * pb[LQ] > R(0) || pb[2] * pb[LQ] > R(0);
+}
+
+// Anti-trapping part: subtracts (pi eps/4) J_i from Phi_i.
+template <typename R, bool ZF, typename KP, typename CP>
+__device__ __forceinline__ void mu_face_j(const KP& P, const CP& C, const R pb[NP], const R gn[NP],
+                                          const R gt1[NP], const R gt2[NP], const R dph[3],
+                                          const R mL[NM], const R mU[NM], R Phi[NM]) {
   const R mb0 = R(0.5) * (mL[0] + mU[0]), mb1 = R(0.5) * (mL[1] + mU[1]);
   const R gl2 = gn[LQ] * gn[LQ] + gt1[LQ] * gt1[LQ] + gt2[LQ] * gt2[LQ];
   if (!(gl2 > R(0))) return;
@@ -322,6 +335,15 @@ __device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP]
   }
   Phi[0] -= (R)P.pieps4 * J0;
   Phi[1] -= (R)P.pieps4 * J1;
+}
+
+// Whole face flux Phi_i = M_i d mu_i - (pi eps/4) J_i.
+template <typename R, bool ZF, typename KP, typename CP>
+__device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP], const R gn[NP],
+                                        const R gt1[NP], const R gt2[NP], const R dph[3],
+                                        const R mL[NM], const R mU[NM], R Phi[NM]) {
+  mu_face_diff<R, ZF>(P, C, pb, mL, mU, Phi);
+  if (P.antitrap && mu_face_needs_j(pb)) mu_face_j<R, ZF>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
 }
 
 // ---------------------------------------------------------- mu cell stage

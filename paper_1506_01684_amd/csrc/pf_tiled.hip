@@ -65,14 +65,41 @@ struct LdsPhi<float, NSLOT> {
   }
 };
 
-// Per-item geometry of one thread.
+// LDS plane of mu^n (one slot, tile plus halo ring): 16-byte (FP64) or
+// 8-byte (FP32) pairs per cell.
+template <typename R>
+struct LdsMu;
+template <>
+struct LdsMu<double> {
+  double2 m[kMaxHalo];
+  __device__ __forceinline__ void get(int c, double out[NM]) const {
+    const double2 v = m[c];
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+  __device__ __forceinline__ void put(int c, const double v[NM]) { m[c] = make_double2(v[0], v[1]); }
+};
+template <>
+struct LdsMu<float> {
+  float2 m[kMaxHalo];
+  __device__ __forceinline__ void get(int c, float out[NM]) const {
+    const float2 v = m[c];
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+  __device__ __forceinline__ void put(int c, const float v[NM]) { m[c] = make_float2(v[0], v[1]); }
+};
+
+// Per-item geometry of one thread.  In-plane offsets are byte offsets that
+// fit 32 bits; plane and field offsets are added to uniform base pointers,
+// so loads take the scalar-base + 32-bit vector-offset form.
 struct TileGeo {
   int tx, ty, lx, ly, x0, y0, z0, z1;
   bool item_ok, valid;
   int own_c;        // LDS index of the own column
-  int64_t own_off;  // in-plane offset of the own column (wrapped for idle threads)
+  uint32_t own_b;   // in-plane byte offset of the own column (wrapped for idle threads)
   int halo_c;       // LDS index of the halo cell this thread loads (-1: none)
-  int64_t halo_off;
+  uint32_t halo_b;
   __device__ __forceinline__ int ci(int cx, int cy) const { return cy * (tx + 2) + cx; }
 };
 
@@ -81,7 +108,7 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-template <typename DD>
+template <typename R, typename DD>
 __device__ __forceinline__ TileGeo make_tile(const DD& d, int local, int t) {
   TileGeo G;
   const WorkTile w = decode_item(d, local, t);
@@ -97,10 +124,10 @@ __device__ __forceinline__ TileGeo make_tile(const DD& d, int local, int t) {
   G.valid = w.valid;
   G.own_c = G.ci(w.lx + 1, w.ly + 1);
   const int gx = wrap_mod(w.x, d.nx), gy = wrap_mod(w.y, d.ny);
-  G.own_off = (int64_t)gy * d.pitch + gx;
+  G.own_b = (uint32_t)(((int64_t)gy * d.pitch + gx) * (int64_t)sizeof(R));
   const int nhalo = 2 * (G.tx + 2) + 2 * G.ty;
   G.halo_c = -1;
-  G.halo_off = 0;
+  G.halo_b = 0;
   if (t < nhalo) {
     int cx, cy;
     if (t < G.tx + 2) {
@@ -118,16 +145,34 @@ __device__ __forceinline__ TileGeo make_tile(const DD& d, int local, int t) {
     }
     G.halo_c = G.ci(cx, cy);
     const int hx = wrap_mod(G.x0 - 1 + cx, d.nx), hy = wrap_mod(G.y0 - 1 + cy, d.ny);
-    G.halo_off = (int64_t)hy * d.pitch + hx;
+    G.halo_b = (uint32_t)(((int64_t)hy * d.pitch + hx) * (int64_t)sizeof(R));
   }
   return G;
 }
 
 template <typename R>
-__device__ __forceinline__ V4<R> load4(const PF_GLOBAL R* base, int64_t fstride, int64_t off) {
+__device__ __forceinline__ R ldg(const PF_GLOBAL char* base, uint32_t boff) {
+  return *reinterpret_cast<const PF_GLOBAL R*>(base + boff);
+}
+template <typename R>
+__device__ __forceinline__ void stg(PF_GLOBAL char* base, uint32_t boff, R v) {
+  *reinterpret_cast<PF_GLOBAL R*>(base + boff) = v;
+}
+
+// Fields of one copy: field f of plane k starts at b + f fsb + k plb.
+struct Copy {
+  PF_GLOBAL char* b;
+  int64_t fsb, plb;
+  __device__ __forceinline__ PF_GLOBAL char* at(int f, int k) const {
+    return b + f * fsb + (int64_t)k * plb;
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ V4<R> load4(const Copy& c, int k, uint32_t boff) {
   V4<R> v;
 #pragma unroll
-  for (int a = 0; a < NP; ++a) v.v[a] = base[a * fstride + off];
+  for (int a = 0; a < NP; ++a) v.v[a] = ldg<R>(c.at(a, k), boff);
   return v;
 }
 
@@ -135,14 +180,13 @@ __device__ __forceinline__ int slot_of(int nslot, int plane) {
   return nslot == 1 ? 0 : (plane + 3) % 3;
 }
 
-// Face inputs from LDS: face between LDS cells (cx,cy) and its upper
-// neighbour along D, planes given by slots (sm, s0, sp) = (k-1, k, k+1) for
-// x/y faces, (s0, sp) = (k, k+1) for z faces.  FULL adds the tangential
-// components (4-point averages of central differences).
-template <typename R, int D, bool FULL, int NSLOT>
-__device__ __forceinline__ void lds_face(const LdsPhi<R, NSLOT>& S, const TileGeo& G, int cx,
-                                         int cy, int sm, int s0, int sp, R inv_dx, R inv_4dx,
-                                         R pb[NP], R gn[NP], R gt1[NP], R gt2[NP]) {
+// Face values of phi from LDS: the face between LDS cells (cx,cy) and its
+// upper neighbour along D (slot s0 = plane k; for D = 2 the upper cell is in
+// slot sp = plane k+1): face average pb and normal difference gn.
+template <typename R, int D, int NSLOT>
+__device__ __forceinline__ void lds_face_normal(const LdsPhi<R, NSLOT>& S, const TileGeo& G,
+                                                int cx, int cy, int s0, int sp, R inv_dx,
+                                                R pb[NP], R gn[NP]) {
   const int cL = G.ci(cx, cy);
   const int cU = D == 0 ? G.ci(cx + 1, cy) : (D == 1 ? G.ci(cx, cy + 1) : cL);
   const V4<R> L = S.get(s0, cL);
@@ -151,43 +195,51 @@ __device__ __forceinline__ void lds_face(const LdsPhi<R, NSLOT>& S, const TileGe
   for (int a = 0; a < NP; ++a) {
     pb[a] = R(0.5) * (L.v[a] + U.v[a]);
     gn[a] = (U.v[a] - L.v[a]) * inv_dx;
-    gt1[a] = gt2[a] = R(0);
   }
-  if constexpr (FULL) {
-    V4<R> p1L, p1U, m1L, m1U, p2L, p2U, m2L, m2U;
-    if constexpr (D == 0) {  // tangential y (in plane), z (slots)
-      p1L = S.get(s0, G.ci(cx, cy + 1));
-      p1U = S.get(s0, G.ci(cx + 1, cy + 1));
-      m1L = S.get(s0, G.ci(cx, cy - 1));
-      m1U = S.get(s0, G.ci(cx + 1, cy - 1));
-      p2L = S.get(sp, cL);
-      p2U = S.get(sp, cU);
-      m2L = S.get(sm, cL);
-      m2U = S.get(sm, cU);
-    } else if constexpr (D == 1) {  // tangential x, z
-      p1L = S.get(s0, G.ci(cx + 1, cy));
-      p1U = S.get(s0, G.ci(cx + 1, cy + 1));
-      m1L = S.get(s0, G.ci(cx - 1, cy));
-      m1U = S.get(s0, G.ci(cx - 1, cy + 1));
-      p2L = S.get(sp, cL);
-      p2U = S.get(sp, cU);
-      m2L = S.get(sm, cL);
-      m2U = S.get(sm, cU);
-    } else {  // tangential x, y; L in plane k (s0), U in plane k+1 (sp)
-      p1L = S.get(s0, G.ci(cx + 1, cy));
-      p1U = S.get(sp, G.ci(cx + 1, cy));
-      m1L = S.get(s0, G.ci(cx - 1, cy));
-      m1U = S.get(sp, G.ci(cx - 1, cy));
-      p2L = S.get(s0, G.ci(cx, cy + 1));
-      p2U = S.get(sp, G.ci(cx, cy + 1));
-      m2L = S.get(s0, G.ci(cx, cy - 1));
-      m2U = S.get(sp, G.ci(cx, cy - 1));
-    }
+}
+
+// Tangential face gradient components (axes in increasing order, skipping
+// D), each the average of the central differences of the two face cells
+// (4-point stencil); slots (sm, s0, sp) = planes (k-1, k, k+1).
+template <typename R, int D, int NSLOT>
+__device__ __forceinline__ void lds_face_tangential(const LdsPhi<R, NSLOT>& S, const TileGeo& G,
+                                                    int cx, int cy, int sm, int s0, int sp,
+                                                    R inv_4dx, R gt1[NP], R gt2[NP]) {
+  const int cL = G.ci(cx, cy);
+  const int cU = D == 0 ? G.ci(cx + 1, cy) : (D == 1 ? G.ci(cx, cy + 1) : cL);
+  V4<R> p1L, p1U, m1L, m1U, p2L, p2U, m2L, m2U;
+  if constexpr (D == 0) {  // tangential y (in plane), z (slots)
+    p1L = S.get(s0, G.ci(cx, cy + 1));
+    p1U = S.get(s0, G.ci(cx + 1, cy + 1));
+    m1L = S.get(s0, G.ci(cx, cy - 1));
+    m1U = S.get(s0, G.ci(cx + 1, cy - 1));
+    p2L = S.get(sp, cL);
+    p2U = S.get(sp, cU);
+    m2L = S.get(sm, cL);
+    m2U = S.get(sm, cU);
+  } else if constexpr (D == 1) {  // tangential x, z
+    p1L = S.get(s0, G.ci(cx + 1, cy));
+    p1U = S.get(s0, G.ci(cx + 1, cy + 1));
+    m1L = S.get(s0, G.ci(cx - 1, cy));
+    m1U = S.get(s0, G.ci(cx - 1, cy + 1));
+    p2L = S.get(sp, cL);
+    p2U = S.get(sp, cU);
+    m2L = S.get(sm, cL);
+    m2U = S.get(sm, cU);
+  } else {  // tangential x, y; L in plane k (s0), U in plane k+1 (sp)
+    p1L = S.get(s0, G.ci(cx + 1, cy));
+    p1U = S.get(sp, G.ci(cx + 1, cy));
+    m1L = S.get(s0, G.ci(cx - 1, cy));
+    m1U = S.get(sp, G.ci(cx - 1, cy));
+    p2L = S.get(s0, G.ci(cx, cy + 1));
+    p2U = S.get(sp, G.ci(cx, cy + 1));
+    m2L = S.get(s0, G.ci(cx, cy - 1));
+    m2U = S.get(sp, G.ci(cx, cy - 1));
+  }
 #pragma unroll
-    for (int a = 0; a < NP; ++a) {
-      gt1[a] = ((p1L.v[a] + p1U.v[a]) - (m1L.v[a] + m1U.v[a])) * inv_4dx;
-      gt2[a] = ((p2L.v[a] + p2U.v[a]) - (m2L.v[a] + m2U.v[a])) * inv_4dx;
-    }
+  for (int a = 0; a < NP; ++a) {
+    gt1[a] = ((p1L.v[a] + p1U.v[a]) - (m1L.v[a] + m1U.v[a])) * inv_4dx;
+    gt2[a] = ((p2L.v[a] + p2U.v[a]) - (m2L.v[a] + m2U.v[a])) * inv_4dx;
   }
 }
 
@@ -198,9 +250,7 @@ struct ItemCtx {
   TileGeo G;
   Geo g;
   const PF_CONST PlaneCoef<R>* tab;
-  const PF_GLOBAL R* src;
-  PF_GLOBAL R* dst;
-  int64_t fs, plane;
+  Copy src, dst;
 };
 
 template <typename R>
@@ -210,14 +260,13 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   const PF_CONST DevDomain& d = domain_at(doms, di);
   if (!d.active) return false;  // uniform over the work group
   X.dp = &d;
-  X.G = make_tile(d, item - first_item(first, di), t);
+  X.G = make_tile<R>(d, item - first_item(first, di), t);
   if (!X.G.item_ok) return false;  // padding block (uniform)
   X.g = make_geo(d);
   X.tab = to_const(static_cast<const PlaneCoef<R>*>(d.coef));
-  X.src = to_global(static_cast<const R*>(d.copy[d.cur_src]));
-  X.dst = to_global(static_cast<R*>(d.copy[d.cur_src ^ 1]));
-  X.fs = d.fstride;
-  X.plane = d.plane;
+  const int64_t fsb = d.fstride * (int64_t)sizeof(R), plb = d.plane * (int64_t)sizeof(R);
+  X.src = Copy{to_global(static_cast<char*>(d.copy[d.cur_src])), fsb, plb};
+  X.dst = Copy{to_global(static_cast<char*>(d.copy[d.cur_src ^ 1])), fsb, plb};
   return true;
 }
 
@@ -240,22 +289,18 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const auto& P = kparams<R>(*X.dp);
-    const PF_GLOBAL R* src = X.src;
-    PF_GLOBAL R* dst = X.dst;
-    const int64_t fs = X.fs, pl = X.plane;
-    const PF_GLOBAL R* mu0 = src + 4 * fs;
-    const PF_GLOBAL R* mu1 = src + 5 * fs;
+    const Copy& src = X.src;
+    const Copy& dst = X.dst;
     const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
     const int kstart = G.z0 - 1;
 
     // prime the LDS ring with planes kstart-1 .. kstart+1 (ANISO) or kstart
     for (int p = kstart - (NSLOT == 3 ? 1 : 0); p <= kstart + (NSLOT == 3 ? 1 : 0); ++p) {
-      const int64_t po = (int64_t)g.zc(p) * pl;
-      const int sl = slot_of(NSLOT, p);
-      s_phi.put(sl, G.own_c, load4(src, fs, po + G.own_off));
-      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4(src, fs, po + G.halo_off));
+      const int pc = g.zc(p), sl = slot_of(NSLOT, p);
+      s_phi.put(sl, G.own_c, load4<R>(src, pc, G.own_b));
+      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4<R>(src, pc, G.halo_b));
     }
-    V4<R> own_k = load4(src, fs, (int64_t)g.zc(kstart) * pl + G.own_off);
+    V4<R> own_k = load4<R>(src, g.zc(kstart), G.own_b);
     __syncthreads();
 
     R Fzl[NP], Szl[NP];  // z face below the current plane
@@ -266,15 +311,14 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       const bool cells = k >= G.z0;  // kstart only evaluates the z face above it
       const int sm = slot_of(NSLOT, k - 1), s0 = slot_of(NSLOT, k), sp = slot_of(NSLOT, k + 1);
       // issue the loads of plane k+AHEAD (own column and halo cell)
-      const int64_t pa = (int64_t)g.zc(k + AHEAD) * pl;
-      const V4<R> nxt_own = load4(src, fs, pa + G.own_off);
+      const int pa = g.zc(k + AHEAD);
+      const V4<R> nxt_own = load4<R>(src, pa, G.own_b);
       V4<R> nxt_halo;
-      if (G.halo_c >= 0) nxt_halo = load4(src, fs, pa + G.halo_off);
+      if (G.halo_c >= 0) nxt_halo = load4<R>(src, pa, G.halo_b);
       R mc[NM] = {R(0), R(0)};
       if (cells) {
-        const int64_t o = (int64_t)k * pl + G.own_off;
-        mc[0] = mu0[o];
-        mc[1] = mu1[o];
+        mc[0] = ldg<R>(src.at(4, k), G.own_b);
+        mc[1] = ldg<R>(src.at(5, k), G.own_b);
         // x faces: own upper face, plus the tile's lower edge face for the
         // first ty threads (same code path for both)
 #pragma unroll 1
@@ -283,8 +327,9 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           if (edge ? !(t < G.ty && G.y0 + t < g.ny) : !G.valid) continue;
           const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
           const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
-          R pb[NP], gn[NP], gt1[NP], gt2[NP], F[NP], S[NP];
-          lds_face<R, 0, ANISO>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
+          R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP], S[NP];
+          lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
+          if constexpr (ANISO) lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
           phi_face<R, ANISO, 0>(P, pb, gn, gt1, gt2, F, S);
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
@@ -298,8 +343,9 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           if (edge ? !(t < G.tx && G.x0 + t < g.nx) : !G.valid) continue;
           const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
           const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
-          R pb[NP], gn[NP], gt1[NP], gt2[NP], F[NP], S[NP];
-          lds_face<R, 1, ANISO>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
+          R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP], S[NP];
+          lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
+          if constexpr (ANISO) lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
           phi_face<R, ANISO, 1>(P, pb, gn, gt1, gt2, F, S);
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
@@ -314,17 +360,16 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) Fzu[a] = Szu[a] = R(0);
       } else {
-        R pb[NP], gn[NP], gt1[NP], gt2[NP];
+        R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {};
         if constexpr (ANISO) {
-          lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_dx, inv_4dx, pb, gn,
-                               gt1, gt2);
+          lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
+          lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
         } else {
           // own column at k (registers) and k+1 (just loaded)
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
             pb[a] = R(0.5) * (own_k.v[a] + nxt_own.v[a]);
             gn[a] = (nxt_own.v[a] - own_k.v[a]) * inv_dx;
-            gt1[a] = gt2[a] = R(0);
           }
         }
         phi_face<R, ANISO, 2>(P, pb, gn, gt1, gt2, Fzu, Szu);
@@ -355,9 +400,8 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
         }
         double out[NP];
         phi_cell<R>(P, X.tab[k], ownv.v, mc, Ss, Fd, out);
-        const int64_t o = (int64_t)k * pl + G.own_off;
 #pragma unroll
-        for (int a = 0; a < NP; ++a) dst[a * fs + o] = (R)out[a];
+        for (int a = 0; a < NP; ++a) stg<R>(dst.at(a, k), G.own_b, (R)out[a]);
       }
 #pragma unroll
       for (int a = 0; a < NP; ++a) {
@@ -372,12 +416,22 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
 
 // ============================================================= mu-sweep
 
+// phi^{n+1} differences of the solid phases on a face, for dphi/dt.
+template <typename R>
+__device__ __forceinline__ void face_dphi(const Copy& p1, int k, uint32_t bL, uint32_t bU,
+                                          const V4<R>& L0, const V4<R>& U0, R dph[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    dph[a] = (ldg<R>(p1.at(a, k), bL) - L0.v[a]) + (ldg<R>(p1.at(a, k), bU) - U0.v[a]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const* doms,
                                                                 const int32_t* first, int ndom,
                                                                 int total) {
   constexpr int NSLOT = 3, AHEAD = 2;
   __shared__ LdsPhi<R, NSLOT> s_phi;
+  __shared__ LdsMu<R> s_mu;  // mu^n of plane k
   __shared__ R s_fx[NM][kMaxFx];
   __shared__ R s_fy[NM][kMaxFy];
   const int t = threadIdx.x;
@@ -388,70 +442,76 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const auto& P = kparams<R>(*X.dp);
-    const PF_GLOBAL R* src = X.src;
-    PF_GLOBAL R* dst = X.dst;
-    const int64_t fs = X.fs, pl = X.plane;
-    const PF_GLOBAL R* p1 = dst;  // phi^{n+1}, written by the phi-sweep
-    const PF_GLOBAL R* mu0 = src + 4 * fs;
-    const PF_GLOBAL R* mu1 = src + 5 * fs;
-    PF_GLOBAL R* mo0 = dst + 4 * fs;
-    PF_GLOBAL R* mo1 = dst + 5 * fs;
+    const Copy& src = X.src;  // phi^n (fields 0-3), mu^n (4-5)
+    const Copy& dst = X.dst;  // phi^{n+1} (written by the phi-sweep), mu^{n+1}
     const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
+    const bool antitrap = P.antitrap != 0;
     const int kstart = G.z0 - 1;
 
     if (P.mu_frozen) {  // mu^{n+1} = mu^n (tests of the phi part only)
       if (G.valid)
         for (int k = G.z0; k < G.z1; ++k) {
-          const int64_t o = (int64_t)k * pl + G.own_off;
-          mo0[o] = mu0[o];
-          mo1[o] = mu1[o];
+          stg<R>(dst.at(4, k), G.own_b, ldg<R>(src.at(4, k), G.own_b));
+          stg<R>(dst.at(5, k), G.own_b, ldg<R>(src.at(5, k), G.own_b));
         }
       continue;
     }
 
-    // in-plane offsets of the face partners (x+1 / y+1 of the own column;
-    // the tile's lower-edge faces use x0-1 / y0-1)
+    // in-plane byte offsets of the face partners (x+1 / y+1 of the own
+    // column; the tile's lower-edge faces use x0-1 / y0-1)
+    const int64_t esz = sizeof(R);
     const int gx = G.x0 + G.lx, gy = G.y0 + G.ly;
-    const int64_t off_xu = G.valid ? (int64_t)gy * g.pitch + g.xp(gx) : G.own_off;
-    const int64_t off_yu = G.valid ? (int64_t)g.yp(gy) * g.pitch + gx : G.own_off;
-    int64_t edge_xL = 0, edge_xU = 0, edge_yL = 0, edge_yU = 0;
+    const uint32_t b_xu = G.valid ? (uint32_t)(((int64_t)gy * g.pitch + g.xp(gx)) * esz) : G.own_b;
+    const uint32_t b_yu = G.valid ? (uint32_t)(((int64_t)g.yp(gy) * g.pitch + gx) * esz) : G.own_b;
+    uint32_t b_exL = 0, b_exU = 0, b_eyL = 0, b_eyU = 0;
     const bool ex = t < G.ty && G.y0 + t < g.ny;
     const bool ey = t < G.tx && G.x0 + t < g.nx;
     if (ex) {
-      edge_xL = (int64_t)(G.y0 + t) * g.pitch + g.xm(G.x0);
-      edge_xU = (int64_t)(G.y0 + t) * g.pitch + G.x0;
+      b_exL = (uint32_t)(((int64_t)(G.y0 + t) * g.pitch + g.xm(G.x0)) * esz);
+      b_exU = (uint32_t)(((int64_t)(G.y0 + t) * g.pitch + G.x0) * esz);
     }
     if (ey) {
-      edge_yL = (int64_t)g.ym(G.y0) * g.pitch + G.x0 + t;
-      edge_yU = (int64_t)G.y0 * g.pitch + G.x0 + t;
+      b_eyL = (uint32_t)(((int64_t)g.ym(G.y0) * g.pitch + G.x0 + t) * esz);
+      b_eyU = (uint32_t)(((int64_t)G.y0 * g.pitch + G.x0 + t) * esz);
     }
 
     for (int p = kstart - 1; p <= kstart + 1; ++p) {
-      const int64_t po = (int64_t)g.zc(p) * pl;
-      const int sl = slot_of(NSLOT, p);
-      s_phi.put(sl, G.own_c, load4(src, fs, po + G.own_off));
-      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4(src, fs, po + G.halo_off));
+      const int pc = g.zc(p), sl = slot_of(NSLOT, p);
+      s_phi.put(sl, G.own_c, load4<R>(src, pc, G.own_b));
+      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4<R>(src, pc, G.halo_b));
     }
-    // phi^{n+1} and mu^n of the own column at plane kstart
-    const int64_t ok = (int64_t)g.zc(kstart) * pl + G.own_off;
-    V4<R> own1 = load4(p1, fs, ok);
-    R ownm[NM] = {mu0[ok], mu1[ok]};
+    // mu^n of plane kstart into LDS (own column also kept in registers),
+    // phi^{n+1} of the own column at plane kstart
+    const int kc0 = g.zc(kstart);
+    R ownm[NM] = {ldg<R>(src.at(4, kc0), G.own_b), ldg<R>(src.at(5, kc0), G.own_b)};
+    s_mu.put(G.own_c, ownm);
+    if (G.halo_c >= 0) {
+      const R hm[NM] = {ldg<R>(src.at(4, kc0), G.halo_b), ldg<R>(src.at(5, kc0), G.halo_b)};
+      s_mu.put(G.halo_c, hm);
+    }
+    V4<R> own1 = load4<R>(dst, kc0, G.own_b);
     __syncthreads();
 
     R Pzl[NM] = {R(0), R(0)};
     for (int k = kstart; k < G.z1; ++k) {
       const bool cells = k >= G.z0;
       const int sm = slot_of(NSLOT, k - 1), s0 = slot_of(NSLOT, k), sp = slot_of(NSLOT, k + 1);
-      const int64_t pa = (int64_t)g.zc(k + AHEAD) * pl;
-      const V4<R> nxt_own = load4(src, fs, pa + G.own_off);
+      const int pa = g.zc(k + AHEAD);
+      const V4<R> nxt_own = load4<R>(src, pa, G.own_b);
       V4<R> nxt_halo;
-      if (G.halo_c >= 0) nxt_halo = load4(src, fs, pa + G.halo_off);
-      // own column at k+1: phi^{n+1}, mu^n (for the z face above k)
-      const int64_t o1 = (int64_t)g.zp(k) * pl + G.own_off;
-      const V4<R> up1 = load4(p1, fs, o1);
-      const R upm[NM] = {mu0[o1], mu1[o1]};
-      const int64_t pk = (int64_t)(k < 0 ? 0 : k) * pl;
-      const auto& C = X.tab[k < 0 ? 0 : k];
+      if (G.halo_c >= 0) nxt_halo = load4<R>(src, pa, G.halo_b);
+      // plane k+1: mu^n (own column and halo cell; the own value also feeds
+      // the z face above k) and phi^{n+1} of the own column
+      const int k1 = g.zp(k);
+      const R upm[NM] = {ldg<R>(src.at(4, k1), G.own_b), ldg<R>(src.at(5, k1), G.own_b)};
+      R nxt_hm[NM] = {R(0), R(0)};
+      if (G.halo_c >= 0) {
+        nxt_hm[0] = ldg<R>(src.at(4, k1), G.halo_b);
+        nxt_hm[1] = ldg<R>(src.at(5, k1), G.halo_b);
+      }
+      const V4<R> up1 = load4<R>(dst, k1, G.own_b);
+      const int kk = k < 0 ? 0 : k;
+      const auto& C = X.tab[kk];
       if (cells) {
 #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
@@ -459,19 +519,19 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           if (edge ? !ex : !G.valid) continue;
           const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
           const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
-          const int64_t oL = pk + (edge ? edge_xL : G.own_off);
-          const int64_t oU = pk + (edge ? edge_xU : off_xu);
-          R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3], mL[NM], mU[NM], Phi[NM];
-          lds_face<R, 0, true>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
-          const V4<R> L0 = s_phi.get(s0, G.ci(cx, cy)), U0 = s_phi.get(s0, G.ci(cx + 1, cy));
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-            dph[a] = (p1[a * fs + oL] - L0.v[a]) + (p1[a * fs + oU] - U0.v[a]);
-          mL[0] = mu0[oL];
-          mL[1] = mu1[oL];
-          mU[0] = mu0[oU];
-          mU[1] = mu1[oU];
-          mu_face<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          const uint32_t bL = edge ? b_exL : G.own_b, bU = edge ? b_exU : b_xu;
+          R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
+          lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
+          s_mu.get(G.ci(cx, cy), mL);
+          s_mu.get(G.ci(cx + 1, cy), mU);
+          mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+          if (antitrap && mu_face_needs_j(pb)) {
+            R gt1[NP], gt2[NP], dph[3];
+            lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+            face_dphi<R>(dst, k, bL, bU, s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)),
+                         dph);
+            mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          }
           s_fx[0][fo] = Phi[0];
           s_fx[1][fo] = Phi[1];
         }
@@ -481,19 +541,19 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           if (edge ? !ey : !G.valid) continue;
           const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
           const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
-          const int64_t oL = pk + (edge ? edge_yL : G.own_off);
-          const int64_t oU = pk + (edge ? edge_yU : off_yu);
-          R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3], mL[NM], mU[NM], Phi[NM];
-          lds_face<R, 1, true>(s_phi, G, cx, cy, sm, s0, sp, inv_dx, inv_4dx, pb, gn, gt1, gt2);
-          const V4<R> L0 = s_phi.get(s0, G.ci(cx, cy)), U0 = s_phi.get(s0, G.ci(cx, cy + 1));
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-            dph[a] = (p1[a * fs + oL] - L0.v[a]) + (p1[a * fs + oU] - U0.v[a]);
-          mL[0] = mu0[oL];
-          mL[1] = mu1[oL];
-          mU[0] = mu0[oU];
-          mU[1] = mu1[oU];
-          mu_face<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          const uint32_t bL = edge ? b_eyL : G.own_b, bU = edge ? b_eyU : b_yu;
+          R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
+          lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
+          s_mu.get(G.ci(cx, cy), mL);
+          s_mu.get(G.ci(cx, cy + 1), mU);
+          mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+          if (antitrap && mu_face_needs_j(pb)) {
+            R gt1[NP], gt2[NP], dph[3];
+            lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+            face_dphi<R>(dst, k, bL, bU, s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)),
+                         dph);
+            mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+          }
           s_fy[0][fo] = Phi[0];
           s_fy[1][fo] = Phi[1];
         }
@@ -501,21 +561,27 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
       // z face above plane k
       R Pzu[NM] = {R(0), R(0)};
       if (k >= 0 && k < g.nz - 1) {
-        R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3];
-        lds_face<R, 2, true>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_dx, inv_4dx, pb, gn,
-                             gt1, gt2);
-        const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
+        R pb[NP], gn[NP];
+        lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
+        mu_face_diff<R, true>(P, C, pb, ownm, upm, Pzu);
+        if (antitrap && mu_face_needs_j(pb)) {
+          R gt1[NP], gt2[NP], dph[3];
+          lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
+          const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
-        mu_face<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+          for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
+          mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+        }
       }
       V4<R> own0;
       if (cells) own0 = s_phi.get(s0, G.own_c);
-      __syncthreads();  // B1
+      __syncthreads();  // B1: faces visible; phi slot of k-1 and mu plane k free
       {
         const int sl = slot_of(NSLOT, k + AHEAD);
         s_phi.put(sl, G.own_c, nxt_own);
         if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, nxt_halo);
+        s_mu.put(G.own_c, upm);
+        if (G.halo_c >= 0) s_mu.put(G.halo_c, nxt_hm);
       }
       if (cells && G.valid) {
         const int fl = G.ly * (G.tx + 1) + G.lx;
@@ -529,9 +595,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           div[q] = (div[q] + (Pzu[q] - Pzl[q])) * inv_dx;
         }
         mu_cell<R>(P, C, own0.v, own1.v, ownm, div, out);
-        const int64_t o = (int64_t)k * pl + G.own_off;
-        mo0[o] = out[0];
-        mo1[o] = out[1];
+        stg<R>(dst.at(4, k), G.own_b, out[0]);
+        stg<R>(dst.at(5, k), G.own_b, out[1]);
       }
       Pzl[0] = Pzu[0];
       Pzl[1] = Pzu[1];
