@@ -93,7 +93,12 @@ typedef struct {
   int32_t antitrapping; /* 1: include the anti-trapping current of Eq. (4) */
   int32_t mu_frozen;    /* 1: mu is held fixed (for tests of the phi part) */
   int32_t diag_every;   /* run diagnostics every n steps inside pf_step (0 = never) */
-  int32_t reserved;
+  int32_t shortcuts;    /* 1: skip work whose result is exactly known (Sec. 3.3
+                         * shortcuts, made exact): phi faces whose normal
+                         * differences all vanish carry exactly zero flux, and
+                         * a pure cell with zero face sums that is a fixed
+                         * point of its plane keeps its value.  Results are
+                         * bitwise identical to 0 (evaluate everything). */
 } pf_params;
 
 typedef enum { PF_INIT_VORONOI = 0, PF_INIT_HOST = 1 } pf_init_kind;

@@ -97,6 +97,7 @@ def params_struct(p: dict) -> A.PfParams:
     s.antitrapping = int(p.get("antitrapping", 1))
     s.mu_frozen = int(p.get("mu_frozen", 0))
     s.diag_every = int(p.get("diag_every", 0))
+    s.shortcuts = int(p.get("shortcuts", 1))
     return s
 
 

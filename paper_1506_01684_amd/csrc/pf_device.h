@@ -56,7 +56,9 @@ struct KParams {
   R inv_dx, inv_4dx;
   R dt, half_inv_dt;  // dt, 1/(2 dt)
   R pieps4;           // pi eps / 4
-  int32_t aniso, antitrap, mu_frozen, pad;
+  int32_t aniso, antitrap, mu_frozen, shortcuts;
+  int32_t aniso_mask;  // bit i set: pair i has delta > 0
+  int32_t pad[3];
 };
 
 // Per z-plane coefficients of one step, all evaluated in FP64 and then
@@ -77,6 +79,8 @@ struct PlaneCoef {
   R chi1[NP][NM];       // chi_ai(T^{n+1}_k)
   R dchi[NP][NM];       // chi(T^{n+1}_k) - chi(T^n_k)  (difference in FP64)
   R dcbar[NP][NM];      // cbar(T^{n+1}_k) - cbar(T^n_k)
+  int32_t pure_fixed;   // bit a: a pure-a cell with zero face terms maps to itself
+  int32_t pad;
 };
 
 // Device-resident descriptor of one domain.
@@ -142,7 +146,7 @@ template <typename R, int D>
 __device__ __forceinline__ R aniso_Xd(R qx, R qy, R qz, R delta) {
   const R q[3] = {qx, qy, qz};
   R qq = qx * qx + qy * qy + qz * qz;
-  if (delta == R(0) || qq <= R(1e-30)) return R(2) * q[D];
+  if (qq <= R(1e-30)) return R(2) * q[D];
   R inv = rsq_(qq);
   R qn = qq * inv;
   R hx = qx * inv, hy = qy * inv, hz = qz * inv;
@@ -170,7 +174,8 @@ __device__ __forceinline__ void phi_face(const KP& P, const R pb[NP], const R gn
     for (int b = a + 1; b < NP; ++b) {
       const int pi = pair_index(a, b);
       R Y;  // gamma_ab X_ab.e_D
-      if constexpr (ANISO) {
+      // pairs without anisotropy take X.e_D = 2 q.e_D (a uniform branch)
+      if (ANISO && ((P.aniso_mask >> pi) & 1)) {
         // full generalised gradient q = pb_a grad phi_b - pb_b grad phi_a
         R qn = pb[a] * gn[b] - pb[b] * gn[a];
         R q1 = pb[a] * gt1[b] - pb[b] * gt1[a];
@@ -189,6 +194,35 @@ __device__ __forceinline__ void phi_face(const KP& P, const R pb[NP], const R gn
       S[b] -= Y * gn[a];
     }
   }
+}
+
+// Exact shortcut tests (the paper's shortcuts, Sec. 3.3, restricted to work
+// whose result is known exactly).
+//
+// A phi face whose normal differences all vanish carries F = S = 0 exactly:
+// then q_ab.e_D = 0 for every pair, so X_ab.e_D = 0 also on anisotropic
+// pairs (q_hat.e_D = 0), and S_a sums Y gn_b = 0.
+template <typename R>
+__device__ __forceinline__ bool zero_normal(const R gn[NP]) {
+  return gn[0] == R(0) && gn[1] == R(0) && gn[2] == R(0) && gn[3] == R(0);
+}
+
+// A pure cell (phi = e_a exactly) whose face sums vanish has A = 0, a zero
+// driving force and obstacle derivative 16/pi^2 gamma_ab for the absent
+// phases; when its plane marks e_a as a fixed point of the Euler step and
+// the projection (fixed_mask bit a), its new value is e_a again.
+template <typename R>
+__device__ __forceinline__ bool pure_cell_fixed(const R ph[NP], const R Ss[NP], const R Fd[NP],
+                                                int fixed_mask) {
+#pragma unroll
+  for (int a = 0; a < NP; ++a)
+    if (Ss[a] != R(0) || Fd[a] != R(0)) return false;
+  const int a1 = ph[0] == R(1) ? 0 : (ph[1] == R(1) ? 1 : (ph[2] == R(1) ? 2 : (ph[3] == R(1) ? 3 : -1)));
+  if (a1 < 0) return false;
+  int nonzero = 0;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) nonzero += ph[b] != R(0);
+  return nonzero == 1 && ((fixed_mask >> a1) & 1);
 }
 
 // ------------------------------------------------------------ projection

@@ -80,6 +80,29 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
         c.dchiLZ[a][q] = (R)(chiZ[LQ][q] - chiZ[a][q]);
         c.dcbLZ[a][q] = (R)(cbZ[LQ][q] - cbZ[a][q]);
       }
+    // A pure cell (phi = e_a) whose face terms vanish has rhs_a = 0 and
+    // rhs_b = (T/eps) 16/pi^2 gamma_ab, so after the Euler step
+    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m), m the mean.  The
+    // projection returns e_a exactly when every y_b stays below
+    // y_a - 1 = rate_a m; the margin covers FP32 rounding of y.
+    c.pure_fixed = 0;
+    for (int a = 0; a < NP; ++a) {
+      double rhs[NP], m = 0.0;
+      for (int b = 0; b < NP; ++b) {
+        rhs[b] = b == a ? 0.0 : (Tn / d.eps) * d.kp64.g16[a < b ? pair_index(a, b) : pair_index(b, a)];
+        m += rhs[b];
+      }
+      m *= 0.25;
+      const double thr = d.kp64.rate[a] * m;
+      bool fixed = true;
+      for (int b = 0; b < NP; ++b) {
+        if (b == a) continue;
+        const double yb = -d.kp64.rate[b] * (rhs[b] - m);
+        fixed = fixed && yb + 1e-5 * (fabs(thr) + fabs(yb)) < thr;
+      }
+      if (fixed) c.pure_fixed |= 1 << a;
+    }
+    c.pad = 0;
     tab[k] = c;
   }
   __syncthreads();

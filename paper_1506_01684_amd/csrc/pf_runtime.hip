@@ -284,7 +284,12 @@ void fill_kparams(KParams<R>& k, const pf_params& p, double dt, double dx, bool 
   k.aniso = aniso ? 1 : 0;
   k.antitrap = p.antitrapping ? 1 : 0;
   k.mu_frozen = p.mu_frozen ? 1 : 0;
-  k.pad = 0;
+  k.shortcuts = p.shortcuts ? 1 : 0;
+  k.aniso_mask = 0;
+  for (int a = 0; a < NP; ++a)
+    for (int b = a + 1; b < NP; ++b)
+      if (p.aniso_delta[a][b] > 0.0) k.aniso_mask |= 1 << pair_index(a, b);
+  k.pad[0] = k.pad[1] = k.pad[2] = 0;
 }
 
 pf_status enqueue_step(pf_domain* d, hipEvent_t* ev) {

@@ -292,6 +292,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
     const Copy& src = X.src;
     const Copy& dst = X.dst;
     const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
+    const bool shortcut = P.shortcuts != 0;
     const int kstart = G.z0 - 1;
 
     // prime the LDS ring with planes kstart-1 .. kstart+1 (ANISO) or kstart
@@ -327,10 +328,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           if (edge ? !(t < G.ty && G.y0 + t < g.ny) : !G.valid) continue;
           const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
           const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
-          R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP], S[NP];
+          R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP] = {}, S[NP] = {};
           lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
-          if constexpr (ANISO) lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
-          phi_face<R, ANISO, 0>(P, pb, gn, gt1, gt2, F, S);
+          if (!(shortcut && zero_normal(gn))) {
+            if constexpr (ANISO) lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+            phi_face<R, ANISO, 0>(P, pb, gn, gt1, gt2, F, S);
+          }
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
             s_fx[a][fo] = F[a];
@@ -343,10 +346,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           if (edge ? !(t < G.tx && G.x0 + t < g.nx) : !G.valid) continue;
           const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
           const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
-          R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP], S[NP];
+          R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP] = {}, S[NP] = {};
           lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
-          if constexpr (ANISO) lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
-          phi_face<R, ANISO, 1>(P, pb, gn, gt1, gt2, F, S);
+          if (!(shortcut && zero_normal(gn))) {
+            if constexpr (ANISO) lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+            phi_face<R, ANISO, 1>(P, pb, gn, gt1, gt2, F, S);
+          }
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
             s_fy[a][fo] = F[a];
@@ -355,15 +360,11 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
         }
       }
       // z face above plane k (zero on the z boundaries)
-      R Fzu[NP], Szu[NP];
-      if (k < 0 || k >= g.nz - 1) {
-#pragma unroll
-        for (int a = 0; a < NP; ++a) Fzu[a] = Szu[a] = R(0);
-      } else {
+      R Fzu[NP] = {}, Szu[NP] = {};
+      if (k >= 0 && k < g.nz - 1) {
         R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {};
         if constexpr (ANISO) {
           lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
-          lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
         } else {
           // own column at k (registers) and k+1 (just loaded)
 #pragma unroll
@@ -372,7 +373,11 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
             gn[a] = (nxt_own.v[a] - own_k.v[a]) * inv_dx;
           }
         }
-        phi_face<R, ANISO, 2>(P, pb, gn, gt1, gt2, Fzu, Szu);
+        if (!(shortcut && zero_normal(gn))) {
+          if constexpr (ANISO)
+            lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
+          phi_face<R, ANISO, 2>(P, pb, gn, gt1, gt2, Fzu, Szu);
+        }
       }
       V4<R> ownv;
       if constexpr (ANISO) ownv = s_phi.get(s0, G.own_c);
@@ -399,7 +404,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
           Fd[a] += Fzu[a] - Fzl[a];
         }
         double out[NP];
-        phi_cell<R>(P, X.tab[k], ownv.v, mc, Ss, Fd, out);
+        if (shortcut && pure_cell_fixed(ownv.v, Ss, Fd, X.tab[k].pure_fixed)) {
+#pragma unroll
+          for (int a = 0; a < NP; ++a) out[a] = (double)ownv.v[a];
+        } else {
+          phi_cell<R>(P, X.tab[k], ownv.v, mc, Ss, Fd, out);
+        }
 #pragma unroll
         for (int a = 0; a < NP; ++a) stg<R>(dst.at(a, k), G.own_b, (R)out[a]);
       }

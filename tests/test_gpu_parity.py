@@ -204,3 +204,32 @@ def test_error_paths():
     d.close()
     with pytest.raises(pf.PfError):
         pf.Domain((0, 4, 4))
+
+
+@pytest.mark.parametrize("prec,aniso,nucleating", [("fp64", False, False), ("fp32", True, False),
+                                                   ("fp64", True, True), ("fp32", False, True)])
+def test_shortcuts_are_bitwise_exact(prec, aniso, nucleating):
+    """Skipping exactly-known work (zero-gradient faces, pure fixed-point
+    cells) leaves every value bitwise unchanged.  With a tiny gamma_01 and a
+    fast tau_1, phase 1 nucleates inside pure phase 0, so pure cells are
+    not fixed points and must still be computed."""
+    shape = (40, 48, 70)
+    p = pfinputs.p0_params(solid_height=10, delta_sl=0.05 if aniso else 0.0)
+    if nucleating:
+        p["gamma"][0][1] = p["gamma"][1][0] = 0.01
+        p["tau"] = [1.0, 0.1, 1.0, 1.0]
+    p["dt"] = oracle.default_dt(p, shape)
+    out = {}
+    for sc in (0, 1):
+        q = dict(p)
+        q["shortcuts"] = sc
+        d = gpu_domain(shape, q, prec, 1, voronoi=(17, 9, 10))
+        d.step(15)
+        out[sc] = d.read()
+        d.close()
+    log(f"shortcuts {prec} aniso={aniso} nucleating={nucleating}: "
+        f"max |diff| {np.max(np.abs(out[0][0] - out[1][0])):.1e}")
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    if nucleating:  # the nucleation really happens inside the pure solid
+        solid0 = out[1][0][0, 2] > 0.5
+        assert out[1][0][1, 2][solid0].max() > 0.0
