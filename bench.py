@@ -1,26 +1,33 @@
 """Benchmark of the phase-field time step (phi-sweep + mu-sweep) on one GPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c1]
-                    [--variant 0|1] [--no-cpu] [--no-fp32]
+                    [--variant 0|1] [--shortcuts 0|1] [--no-cpu] [--no-fp32]
+                    [--no-plain] [--no-fp32-error] [--no-pack] [--no-serve]
 
 Headline: the FP64 256x256x512 domain (64 Voronoi seeds, 128 solid layers,
 synthetic parameter set P0, dt a quarter of the stability bound).  One step
 is the prologue, the phi-sweep and the mu-sweep (Algorithm 1 of the paper)
-with fields resident in HBM.  Also reported: the FP32 512x512x1024
-anisotropic domain, and the FP64 CPU oracle timed on a bounded sample of the
-headline workload on the host's cores.
+with fields resident in HBM.  Exact shortcuts are on by default (their
+results are bitwise identical to evaluating everything); the same workload
+with them off is reported as "plain".  Also reported: the FP32 512x512x1024
+anisotropic domain with its error against the FP64 path after 1000 steps,
+the pack of 64 uneven FP32 domains, a serving trace, and the FP64 CPU
+oracle timed on a bounded sample of the headline workload on the host's
+cores.
 
 Prints one JSON line.  MLUP/s = cells * steps / seconds / 1e6 (the paper's
 unit, Sec. 5).  Roofline: algorithmic bytes of the dominant kernel per
 launch (phi-sweep reads phi, mu and writes phi: 10 values per cell;
 mu-sweep reads phi^n, phi^{n+1}, mu and writes mu: 12 values per cell)
-divided by its average HIP-event duration, against 8 TB/s.
+divided by its average HIP-event duration, against 8 TB/s; "traffic" is the
+HBM bytes per launch that rocprofv3 counted for the same kernel sources.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,7 +42,7 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(workload: str, steps: int, warmup: int, variant: int) -> dict:
+def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int = 1) -> dict:
     import torch
 
     import paper_1506_01684_amd as pf
@@ -46,9 +53,10 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int) -> dict:
     cells = nx * ny * nz
     pf.set_variant(variant)
     d = pf.Domain(w["shape"], w["prec"])
-    d.set_params(w["params"])
+    d.set_params(dict(w["params"], shortcuts=shortcuts))
     d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
-    _log(f"[bench] {workload}: {nx}x{ny}x{nz} {w['prec']} dt={d.dt:.6g} warmup {warmup}")
+    _log(f"[bench] {workload}: {nx}x{ny}x{nz} {w['prec']} shortcuts={shortcuts} "
+         f"dt={d.dt:.6g} warmup {warmup}")
     d.step(warmup)
     d.sync()
     torch.cuda.synchronize()
@@ -75,6 +83,69 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int) -> dict:
     step_bytes = (VALUES_PER_CELL["phi"] + VALUES_PER_CELL["mu"]) * esize * cells
     out["step_hbm_frac"] = step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS
     return out
+
+
+def run_fp32_error(steps: int) -> dict:
+    """The FP32-bulk path against the FP64 path on the 512x512x1024
+    anisotropic domain after `steps` steps from the same initial state:
+    max-abs error of phi and max over mu_i of max|dmu_i| / max|mu_i|."""
+    import numpy as np
+
+    import paper_1506_01684_amd as pf
+    import pfinputs
+
+    w = pfinputs.workload("c3")
+    res = {}
+    for prec in ("fp64", "fp32"):
+        _log(f"[bench] c3 {prec}: {steps} steps for the FP32 error")
+        d = pf.Domain(w["shape"], prec)
+        d.set_params(w["params"])
+        d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
+        d.step(steps)
+        res[prec] = d.read()
+        d.close()
+    (p64, m64), (p32, m32) = res["fp64"], res["fp32"]
+    dphi = float(np.max(np.abs(p32 - p64)))
+    dmu = max(float(np.max(np.abs(m32[q] - m64[q]))) / float(np.max(np.abs(m64[q])))
+              for q in range(2))
+    return {"steps": steps, "phi_max_abs": dphi, "mu_rel": dmu,
+            "tolerance": {"phi_max_abs": 2e-4, "mu_rel": 1e-4},
+            "within": bool(dphi <= 2e-4 and dmu <= 1e-4)}
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 over the device sources of the sweeps; a recorded counter
+    measurement is used only while this digest is unchanged."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1506_01684_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (profiles/hbm_traffic.md), each
+    counter scaled by what it reads for a copy of known size; None when no
+    summary matches the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(workload, {}).get(kernel)
+    if not k:
+        return None
+    return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
 
 
 def run_pack(count: int, steps: int, warmup: int) -> dict:
@@ -198,6 +269,11 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-pack", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the timing with shortcuts off")
+    ap.add_argument("--no-fp32-error", action="store_true",
+                    help="skip the 1000-step FP32-vs-FP64 error run")
+    ap.add_argument("--shortcuts", type=int, default=1, choices=[0, 1])
     ap.add_argument("--pack-steps", type=int, default=100)
     ap.add_argument("--serve-count", type=int, default=64)
     ap.add_argument("--full-serving", action="store_true",
@@ -226,9 +302,13 @@ def main():
               "(multi-GPU sharding is described, not built)", file=sys.stderr)
         sys.exit(2)
 
-    main_run = run_gpu(args.workload, args.steps, args.warmup, args.variant)
+    main_run = run_gpu(args.workload, args.steps, args.warmup, args.variant, args.shortcuts)
     dom = "mu" if main_run["mu_ms"] >= main_run["phi_ms"] else "phi"
     achieved = main_run[f"{dom}_gbs"]
+    real = "double" if main_run["prec"] == "fp64" else "float"
+    aniso = "true" if args.workload == "c3" else "false"
+    kname = f"mu_tiled_kernel<{real}>" if dom == "mu" else f"phi_tiled_kernel<{real}, {aniso}>"
+    traffic = recorded_traffic(kname, args.workload) if args.variant == 1 else None
     line = {
         "metric": "MLUP/s of phi+mu step (FP32 vs FP64) + %HBM peak",
         "value": round(main_run["mlups"], 1),
@@ -244,21 +324,30 @@ def main():
         "data": "synthetic (Voronoi-seeded solid lamellae under liquid, parameter set P0)",
         "config": {
             "workload": f"{args.workload}: {'x'.join(map(str, main_run['shape']))} cells, "
-                        f"{main_run['prec']}, N=4 phases, K-1=2 mu, plain method",
-            "cells": main_run["cells"], "variant": args.variant,
+                        f"{main_run['prec']}, N=4 phases, K-1=2 mu",
+            "cells": main_run["cells"], "variant": args.variant, "shortcuts": args.shortcuts,
             "hbm_frac_step": round(main_run["step_hbm_frac"], 4),
             "phi_sweep_ms": round(main_run["phi_ms"], 4), "mu_sweep_ms": round(main_run["mu_ms"], 4),
             "phi_sweep_gbs": round(main_run["phi_gbs"], 1), "mu_sweep_gbs": round(main_run["mu_gbs"], 1),
         },
         "roofline": {
-            "bound": "hbm", "kernel": f"{dom}_sweep",
+            "bound": "hbm", "kernel": kname,
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
             "bytes_per_launch": main_run[f"{dom}_bytes_per_launch"],
         },
     }
+    if not args.no_plain and args.shortcuts == 1:
+        rp = run_gpu(args.workload, args.steps, args.warmup, args.variant, shortcuts=0)
+        line["plain"] = {
+            "note": "same workload with every face and cell evaluated (shortcuts off; "
+                    "results are bitwise identical)",
+            "mlups": round(rp["mlups"], 1), "ms_per_step": round(rp["ms_per_step"], 4),
+            "phi_sweep_ms": round(rp["phi_ms"], 4), "mu_sweep_ms": round(rp["mu_ms"], 4),
+        }
     if not args.no_fp32 and args.workload == "c2":
-        r32 = run_gpu("c3", args.fp32_steps, 5, args.variant)
+        r32 = run_gpu("c3", args.fp32_steps, 5, args.variant, args.shortcuts)
         line["fp32"] = {
             "workload": "c3: 512x512x1024 cells, fp32 bulk, cubic anisotropy 0.05",
             "mlups": round(r32["mlups"], 1), "ms_per_step": round(r32["ms_per_step"], 4),
@@ -267,6 +356,11 @@ def main():
             "phi_sweep_gbs": round(r32["phi_gbs"], 1), "mu_sweep_gbs": round(r32["mu_gbs"], 1),
             "steps": args.fp32_steps,
         }
+        if not args.no_plain and args.shortcuts == 1:
+            rp = run_gpu("c3", args.fp32_steps, 5, args.variant, shortcuts=0)
+            line["fp32"]["plain_mlups"] = round(rp["mlups"], 1)
+        if not args.no_fp32_error:
+            line["fp32"]["error_vs_fp64"] = run_fp32_error(1000)
     if not args.no_pack and args.workload == "c2":
         _log("[bench] pack of 64 domains")
         line["pack"] = run_pack(64, args.pack_steps, 5)
