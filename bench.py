@@ -307,7 +307,8 @@ def main():
     achieved = main_run[f"{dom}_gbs"]
     real = "double" if main_run["prec"] == "fp64" else "float"
     aniso = "true" if args.workload == "c3" else "false"
-    kname = f"mu_tiled_kernel<{real}>" if dom == "mu" else f"phi_tiled_kernel<{real}, {aniso}>"
+    kname = (f"mu_tiled_f{64 if real == 'double' else 32}" if dom == "mu"
+             else f"phi_tiled_kernel<{real}, {aniso}>")
     traffic = recorded_traffic(kname, args.workload) if args.variant == 1 else None
     line = {
         "metric": "MLUP/s of phi+mu step (FP32 vs FP64) + %HBM peak",

@@ -108,9 +108,12 @@ Tiling choose_tiling(int nx, int ny, int nz) {
   t.ty = kTileThreads / t.tx;
   t.ntx = (nx + t.tx - 1) / t.tx;
   t.nty = (ny + t.ty - 1) / t.ty;
-  const int64_t tiles = (int64_t)t.ntx * t.nty;
-  int64_t zc = ((int64_t)nz * tiles + 4095) / 4096;
-  zc = std::max<int64_t>(8, std::min<int64_t>(256, zc));
+  // z chunk: 32 planes, fewer (down to 8) while that leaves fewer than
+  // ~2048 work items.  Long chunks let neighbouring tiles drift apart in z,
+  // so the halo cells one tile loads are evicted from L2 before its
+  // neighbour reads them; short ones re-load more ring planes.
+  const int64_t cols = (int64_t)nz * t.ntx * t.nty;
+  const int64_t zc = std::min<int64_t>(32, std::max<int64_t>(8, cols / 2048));
   t.zc = (int32_t)std::min<int64_t>(zc, nz);
   t.nzc = (nz + t.zc - 1) / t.zc;
   // y-slab order when it leaves at most 1/8 of the blocks without a tile

@@ -10,9 +10,10 @@
 // one plane to the next and x/y faces are exchanged through LDS):
 //   - each thread evaluates the upper x and y faces of its column and the
 //     z face above its cell;
-//   - the tile's lower-edge x and y faces are evaluated by the first
-//     threads, through the same code path as all other faces of that
-//     direction, so every face rounds identically wherever it is computed;
+//   - the tile's lower-edge x and y faces are evaluated by the first lanes
+//     of one wave, rotating over the planes, through the same code path as
+//     all other faces of that direction, so every face rounds identically
+//     wherever it is computed;
 //   - the next plane's loads are issued before the face stage and written
 //     to LDS after it, so their latency overlaps the arithmetic.
 // LDS layout avoids bank conflicts: phi is stored as 16-byte vectors
@@ -282,6 +283,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
   __shared__ R s_fx[2 * NP][kMaxFx];  // F[0..3], S[0..3] of x faces
   __shared__ R s_fy[2 * NP][kMaxFy];
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     ItemCtx<R> X;
@@ -320,14 +322,19 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       if (cells) {
         mc[0] = ldg<R>(src.at(4, k), G.own_b);
         mc[1] = ldg<R>(src.at(5, k), G.own_b);
-        // x faces: own upper face, plus the tile's lower edge face for the
-        // first ty threads (same code path for both)
+        // x faces: own upper face, plus the tile's lower edge faces, taken
+        // by the first ty lanes of wave (k+1) mod 4 (same code path for
+        // both); y faces likewise with the first tx lanes of wave k mod 4.
+        // Rotating the edge duty over the planes keeps any one wave from
+        // carrying the extra faces of every plane.
+        const bool ex = wave == ((k + 1) & 3) && lane < G.ty && G.y0 + lane < g.ny;
+        const bool ey = wave == (k & 3) && lane < G.tx && G.x0 + lane < g.nx;
 #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
           const bool edge = r == 1;
-          if (edge ? !(t < G.ty && G.y0 + t < g.ny) : !G.valid) continue;
-          const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
-          const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
+          if (edge ? !ex : !G.valid) continue;
+          const int cx = edge ? 0 : G.lx + 1, cy = edge ? lane + 1 : G.ly + 1;
+          const int fo = edge ? lane * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
           R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP] = {}, S[NP] = {};
           lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
           if (!(shortcut && zero_normal(gn))) {
@@ -343,9 +350,9 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
 #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
           const bool edge = r == 1;
-          if (edge ? !(t < G.tx && G.x0 + t < g.nx) : !G.valid) continue;
-          const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
-          const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
+          if (edge ? !ey : !G.valid) continue;
+          const int cx = edge ? lane + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
+          const int fo = edge ? lane : (G.ly + 1) * G.tx + G.lx;
           R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {}, F[NP] = {}, S[NP] = {};
           lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
           if (!(shortcut && zero_normal(gn))) {
@@ -426,25 +433,26 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
 
 // ============================================================= mu-sweep
 
-// phi^{n+1} differences of the solid phases on a face, for dphi/dt.
+// phi^{n+1} - phi^n of the solid phases summed over the two cells of a
+// face, for dphi/dt (both planes from LDS).
 template <typename R>
-__device__ __forceinline__ void face_dphi(const Copy& p1, int k, uint32_t bL, uint32_t bU,
-                                          const V4<R>& L0, const V4<R>& U0, R dph[3]) {
+__device__ __forceinline__ void face_dphi(const V4<R>& L1, const V4<R>& U1, const V4<R>& L0,
+                                          const V4<R>& U0, R dph[3]) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-    dph[a] = (ldg<R>(p1.at(a, k), bL) - L0.v[a]) + (ldg<R>(p1.at(a, k), bU) - U0.v[a]);
+  for (int a = 0; a < 3; ++a) dph[a] = (L1.v[a] - L0.v[a]) + (U1.v[a] - U0.v[a]);
 }
 
 template <typename R>
-__global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const* doms,
-                                                                const int32_t* first, int ndom,
-                                                                int total) {
+__device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int32_t* first, int ndom,
+                                              int total) {
   constexpr int NSLOT = 3, AHEAD = 2;
   __shared__ LdsPhi<R, NSLOT> s_phi;
-  __shared__ LdsMu<R> s_mu;  // mu^n of plane k
+  __shared__ LdsMu<R> s_mu;         // mu^n of plane k
+  __shared__ LdsPhi<R, 1> s_p1;     // phi^{n+1} of plane k
   __shared__ R s_fx[NM][kMaxFx];
   __shared__ R s_fy[NM][kMaxFy];
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     ItemCtx<R> X;
@@ -467,23 +475,10 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
       continue;
     }
 
-    // in-plane byte offsets of the face partners (x+1 / y+1 of the own
-    // column; the tile's lower-edge faces use x0-1 / y0-1)
-    const int64_t esz = sizeof(R);
-    const int gx = G.x0 + G.lx, gy = G.y0 + G.ly;
-    const uint32_t b_xu = G.valid ? (uint32_t)(((int64_t)gy * g.pitch + g.xp(gx)) * esz) : G.own_b;
-    const uint32_t b_yu = G.valid ? (uint32_t)(((int64_t)g.yp(gy) * g.pitch + gx) * esz) : G.own_b;
-    uint32_t b_exL = 0, b_exU = 0, b_eyL = 0, b_eyU = 0;
-    const bool ex = t < G.ty && G.y0 + t < g.ny;
-    const bool ey = t < G.tx && G.x0 + t < g.nx;
-    if (ex) {
-      b_exL = (uint32_t)(((int64_t)(G.y0 + t) * g.pitch + g.xm(G.x0)) * esz);
-      b_exU = (uint32_t)(((int64_t)(G.y0 + t) * g.pitch + G.x0) * esz);
-    }
-    if (ey) {
-      b_eyL = (uint32_t)(((int64_t)g.ym(G.y0) * g.pitch + G.x0 + t) * esz);
-      b_eyU = (uint32_t)(((int64_t)G.y0 * g.pitch + G.x0 + t) * esz);
-    }
+    // lane l of the edge wave takes the lower-edge face of tile row l (x)
+    // or tile column l (y), between x0-1 and x0 / y0-1 and y0
+    const bool ex_ok = lane < G.ty && G.y0 + lane < g.ny;
+    const bool ey_ok = lane < G.tx && G.x0 + lane < g.nx;
 
     for (int p = kstart - 1; p <= kstart + 1; ++p) {
       const int pc = g.zc(p), sl = slot_of(NSLOT, p);
@@ -500,6 +495,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
       s_mu.put(G.halo_c, hm);
     }
     V4<R> own1 = load4<R>(dst, kc0, G.own_b);
+    s_p1.put(0, G.own_c, own1);
+    if (G.halo_c >= 0) s_p1.put(0, G.halo_c, load4<R>(dst, kc0, G.halo_b));
     __syncthreads();
 
     R Pzl[NM] = {R(0), R(0)};
@@ -520,16 +517,19 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
         nxt_hm[1] = ldg<R>(src.at(5, k1), G.halo_b);
       }
       const V4<R> up1 = load4<R>(dst, k1, G.own_b);
+      V4<R> nxt_p1h;
+      if (G.halo_c >= 0) nxt_p1h = load4<R>(dst, k1, G.halo_b);
       const int kk = k < 0 ? 0 : k;
       const auto& C = X.tab[kk];
       if (cells) {
+        const bool ex = ex_ok && wave == ((k + 1) & 3);
+        const bool ey = ey_ok && wave == (k & 3);
 #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
           const bool edge = r == 1;
           if (edge ? !ex : !G.valid) continue;
-          const int cx = edge ? 0 : G.lx + 1, cy = edge ? t + 1 : G.ly + 1;
-          const int fo = edge ? t * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
-          const uint32_t bL = edge ? b_exL : G.own_b, bU = edge ? b_exU : b_xu;
+          const int cx = edge ? 0 : G.lx + 1, cy = edge ? lane + 1 : G.ly + 1;
+          const int fo = edge ? lane * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
           R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
           lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
           s_mu.get(G.ci(cx, cy), mL);
@@ -538,8 +538,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           if (antitrap && mu_face_needs_j(pb)) {
             R gt1[NP], gt2[NP], dph[3];
             lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
-            face_dphi<R>(dst, k, bL, bU, s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)),
-                         dph);
+            face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx + 1, cy)),
+                         s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)), dph);
             mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
           }
           s_fx[0][fo] = Phi[0];
@@ -549,9 +549,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
         for (int r = 0; r < 2; ++r) {
           const bool edge = r == 1;
           if (edge ? !ey : !G.valid) continue;
-          const int cx = edge ? t + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
-          const int fo = edge ? t : (G.ly + 1) * G.tx + G.lx;
-          const uint32_t bL = edge ? b_eyL : G.own_b, bU = edge ? b_eyU : b_yu;
+          const int cx = edge ? lane + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
+          const int fo = edge ? lane : (G.ly + 1) * G.tx + G.lx;
           R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
           lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
           s_mu.get(G.ci(cx, cy), mL);
@@ -560,8 +559,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
           if (antitrap && mu_face_needs_j(pb)) {
             R gt1[NP], gt2[NP], dph[3];
             lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
-            face_dphi<R>(dst, k, bL, bU, s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)),
-                         dph);
+            face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx, cy + 1)),
+                         s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)), dph);
             mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
           }
           s_fy[0][fo] = Phi[0];
@@ -592,6 +591,8 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
         if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, nxt_halo);
         s_mu.put(G.own_c, upm);
         if (G.halo_c >= 0) s_mu.put(G.halo_c, nxt_hm);
+        s_p1.put(0, G.own_c, up1);
+        if (G.halo_c >= 0) s_p1.put(0, G.halo_c, nxt_p1h);
       }
       if (cells && G.valid) {
         const int fl = G.ly * (G.tx + 1) + G.lx;
@@ -618,6 +619,16 @@ __global__ __launch_bounds__(kTileThreads) void mu_tiled_kernel(DevDomain* const
   }
 }
 
+// The FP32 instance is held to 128 VGPRs so that four waves fit per SIMD.
+__global__ __launch_bounds__(kTileThreads) void mu_tiled_f64(DevDomain* const* doms, const int32_t* first,
+                                                             int ndom, int total) {
+  mu_tiled_body<double>(doms, first, ndom, total);
+}
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4))) void mu_tiled_f32(
+    DevDomain* const* doms, const int32_t* first, int ndom, int total) {
+  mu_tiled_body<float>(doms, first, ndom, total);
+}
+
 // --------------------------------------------------------------- launches
 
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
@@ -639,9 +650,9 @@ hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_
 hipError_t launch_mu_tiled(const LaunchSet& L, int prec, hipStream_t s) {
   const int grid = L.total;
   if (prec == 0)
-    mu_tiled_kernel<double><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    mu_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   else
-    mu_tiled_kernel<float><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    mu_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@ def tiling(nx, ny, nz):
     tx = 64 if nx >= 48 else 32
     ty = KTHREADS // tx
     ntx, nty = -(-nx // tx), -(-ny // ty)
-    zc = max(8, min(256, -(-(nz * ntx * nty) // 4096)))
+    cols = nz * ntx * nty
+    zc = min(32, max(8, cols // 2048))
     zc = min(zc, nz)
     nzc = -(-nz // zc)
     rs = -(-nty // 8)
