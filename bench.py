@@ -42,13 +42,18 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int = 1) -> dict:
+def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int = 1,
+            solid_height: int | None = None) -> dict:
     import torch
 
     import paper_1506_01684_amd as pf
     import pfinputs
 
     w = pfinputs.workload(workload)
+    if solid_height is not None:  # same domain, front placed at another height
+        dsl = w["params"]["delta"][0][3]
+        w = dict(w, solid_height=solid_height,
+                 params=pfinputs.p0_params(solid_height=solid_height, delta_sl=dsl))
     nz, ny, nx = w["shape"]
     cells = nx * ny * nz
     pf.set_variant(variant)
@@ -83,6 +88,52 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int
     step_bytes = (VALUES_PER_CELL["phi"] + VALUES_PER_CELL["mu"]) * esize * cells
     out["step_hbm_frac"] = step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS
     return out
+
+
+def run_scenarios(steps: int, variant: int) -> dict:
+    """The headline domain with the solid/liquid front at half height, and
+    entirely solid or liquid (solid height Nz/2, Nz, 0), with the exact
+    shortcuts on and off."""
+    import pfinputs
+
+    nz = pfinputs.workload("c2")["shape"][0]
+    out = {}
+    for name, hs in (("interface", nz // 2), ("solid", nz), ("liquid", 0)):
+        r1 = run_gpu("c2", steps, 5, variant, 1, solid_height=hs)
+        r0 = run_gpu("c2", steps, 5, variant, 0, solid_height=hs)
+        out[name] = {"solid_height": hs, "mlups": round(r1["mlups"], 1),
+                     "plain_mlups": round(r0["mlups"], 1),
+                     "phi_ms": round(r1["phi_ms"], 4), "mu_ms": round(r1["mu_ms"], 4),
+                     "plain_phi_ms": round(r0["phi_ms"], 4), "plain_mu_ms": round(r0["mu_ms"], 4)}
+    return out
+
+
+def run_stream(nbytes: int = 2 << 30, reps: int = 10) -> dict:
+    """STREAM-style device bandwidth with torch kernels on FP32 arrays of
+    nbytes each: copy (b = a, 2 nbytes per pass) and add (b = a + c,
+    3 nbytes per pass), event-timed over `reps` passes."""
+    import torch
+
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    c = torch.ones_like(a)
+    b = torch.empty_like(a)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    copy = 2 * nbytes / timed(lambda: b.copy_(a)) / 1e9
+    add = 3 * nbytes / timed(lambda: torch.add(a, c, out=b)) / 1e9
+    del a, b, c
+    return {"bytes_per_array": nbytes, "copy_gbs": round(copy, 1), "add_gbs": round(add, 1)}
 
 
 def run_fp32_error(steps: int) -> dict:
@@ -274,6 +325,8 @@ def main():
     ap.add_argument("--no-fp32-error", action="store_true",
                     help="skip the 1000-step FP32-vs-FP64 error run")
     ap.add_argument("--shortcuts", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--no-scenarios", action="store_true",
+                    help="skip the interface/solid/liquid timings of the headline domain")
     ap.add_argument("--pack-steps", type=int, default=100)
     ap.add_argument("--serve-count", type=int, default=64)
     ap.add_argument("--full-serving", action="store_true",
@@ -347,6 +400,13 @@ def main():
             "mlups": round(rp["mlups"], 1), "ms_per_step": round(rp["ms_per_step"], 4),
             "phi_sweep_ms": round(rp["phi_ms"], 4), "mu_sweep_ms": round(rp["mu_ms"], 4),
         }
+    stream = run_stream()
+    best = max(stream["copy_gbs"], stream["add_gbs"])
+    line["roofline"]["stream"] = stream
+    line["roofline"]["frac_of_stream"] = round(achieved / best, 4)
+    if not args.no_scenarios and args.workload == "c2":
+        _log("[bench] interface / solid / liquid scenarios")
+        line["scenarios"] = run_scenarios(args.steps // 2, args.variant)
     if not args.no_fp32 and args.workload == "c2":
         r32 = run_gpu("c3", args.fp32_steps, 5, args.variant, args.shortcuts)
         line["fp32"] = {
