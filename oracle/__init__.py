@@ -68,6 +68,9 @@ def lib():
             "orc_phi_sweep": (None, [G, P, _D, _PD, _PD, _PD, i]),
             "orc_mu_sweep": (None, [G, P, _D, _D, _PD, _PD, _PD, _PD, i]),
             "orc_run": (i, [G, P, C.c_int64, C.c_int64, _PD, _PD, i]),
+            "orc_window_shift": (i, [G, C.c_int32, _PD, _PD, _PD]),
+            "orc_run_window": (i, [G, P, C.c_int64, C.c_int64, C.c_int32, _PD,
+                                   C.POINTER(C.c_int64), _PD, _PD, i]),
             "orc_init_voronoi": (None, [G, C.c_uint64, C.c_int32, C.c_int32, _PD, _PD, _PD]),
             "orc_diagnostics": (None, [G, P, _D, _PD, _PD, C.POINTER(OrcDiag)]),
         }
@@ -227,6 +230,29 @@ def run(p, phi, mu, nsteps, step0=0, nthreads=None, dx=1.0):
     if rc != 0:
         raise MemoryError("oracle run: allocation failed")
     return phi, mu
+
+
+def window_shift(phi, mu, zw, mu_fill=(0.0, 0.0), dx=1.0):
+    """One moving-window check and shift; returns (phi, mu, shifted)."""
+    phi, mu = _f64(phi).copy(), _f64(mu).copy()
+    m = _f64(mu_fill).reshape(2)
+    r = lib().orc_window_shift(C.byref(make_grid(_shape_of(phi), dx)), int(zw), _ptr(m),
+                               _ptr(phi), _ptr(mu))
+    return phi, mu, bool(r)
+
+
+def run_window(p, phi, mu, nsteps, zw, mu_fill=(0.0, 0.0), step0=0, shifts=0, nthreads=None,
+               dx=1.0):
+    """nsteps steps with a moving window at plane zw; returns (phi, mu, shifts)."""
+    phi, mu = _f64(phi).copy(), _f64(mu).copy()
+    m = _f64(mu_fill).reshape(2)
+    sh = C.c_int64(int(shifts))
+    rc = lib().orc_run_window(C.byref(make_grid(_shape_of(phi), dx)), C.byref(make_params(p)),
+                              int(step0), int(nsteps), int(zw), _ptr(m), C.byref(sh),
+                              _ptr(phi), _ptr(mu), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("oracle run: allocation failed")
+    return phi, mu, sh.value
 
 
 def init_voronoi(shape, seed, nseeds, solid_height, mu_init=(0.0, 0.0), dx=1.0):

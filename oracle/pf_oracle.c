@@ -509,6 +509,42 @@ int orc_run(const orc_grid* g, const orc_params* p, int64_t step0,
   return 0;
 }
 
+/* ------------------------------------------------------ moving window */
+
+int orc_window_shift(const orc_grid* g, int32_t zw, const double mu_fill[2],
+                     double* phi, double* mu) {
+  const size_t plane = (size_t)g->nx * g->ny, n = ncells(g);
+  const double* pl = phi + (size_t)ORC_LIQ * n + (size_t)zw * plane;
+  double sum = 0.0;
+  for (size_t c = 0; c < plane; ++c) sum += pl[c];
+  if (!(sum < 0.5 * (double)plane)) return 0;
+  for (int a = 0; a < NP; ++a) {
+    double* f = phi + (size_t)a * n;
+    memmove(f, f + plane, sizeof(double) * plane * (size_t)(g->nz - 1));
+    double* top = f + plane * (size_t)(g->nz - 1);
+    for (size_t c = 0; c < plane; ++c) top[c] = a == ORC_LIQ ? 1.0 : 0.0;
+  }
+  for (int q = 0; q < NM; ++q) {
+    double* f = mu + (size_t)q * n;
+    memmove(f, f + plane, sizeof(double) * plane * (size_t)(g->nz - 1));
+    double* top = f + plane * (size_t)(g->nz - 1);
+    for (size_t c = 0; c < plane; ++c) top[c] = mu_fill[q];
+  }
+  return 1;
+}
+
+int orc_run_window(const orc_grid* g, const orc_params* p, int64_t step0,
+                   int64_t nsteps, int32_t zw, const double mu_fill[2],
+                   int64_t* shifts, double* phi, double* mu, int nthreads) {
+  orc_params q = *p;
+  for (int64_t s = step0; s < step0 + nsteps; ++s) {
+    if (zw > 0) *shifts += orc_window_shift(g, zw, mu_fill, phi, mu);
+    q.zoff = p->zoff + (double)(*shifts) * g->dx;
+    if (orc_run(g, &q, s, 1, phi, mu, nthreads) != 0) return -1;
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------ initial state */
 
 void orc_init_voronoi(const orc_grid* g, uint64_t seed, int32_t nseeds,

@@ -110,6 +110,26 @@ void orc_mu_sweep(const orc_grid* g, const orc_params* p, double t0, double t1,
 int orc_run(const orc_grid* g, const orc_params* p, int64_t step0,
             int64_t nsteps, double* phi, double* mu, int nthreads);
 
+/* Moving window (Sec. 3.3; the technique of Vondrous et al. 2014 that the
+ * paper cites): the window follows the solidification front along z.  If
+ * the mean liquid fraction of plane zw (sum over the plane of phi_liquid,
+ * in FP64, x fastest, compared with nx ny / 2) is below one half, the front
+ * has passed zw: every plane moves down by one (the bottom plane, deep in
+ * the solid whose evolution the paper neglects, is dropped), the top plane
+ * becomes liquid (phi = e_liquid) at mu = mu_fill, and 1 is returned (the
+ * caller then counts one more shift, i.e. adds dx to zoff).  Otherwise the
+ * fields are untouched and 0 is returned. */
+int orc_window_shift(const orc_grid* g, int32_t zw, const double mu_fill[2],
+                     double* phi, double* mu);
+
+/* orc_run with a moving window at plane zw (> 0): before each step the
+ * window is checked and shifted as above; shifts counts the shifts made so
+ * far (in and out), and the temperature of step s uses
+ * zoff + shifts dx. */
+int orc_run_window(const orc_grid* g, const orc_params* p, int64_t step0,
+                   int64_t nsteps, int32_t zw, const double mu_fill[2],
+                   int64_t* shifts, double* phi, double* mu, int nthreads);
+
 /* Voronoi-seeded initial state: solid lamellae below solid_height, liquid
  * above, mu = mu_init everywhere. */
 void orc_init_voronoi(const orc_grid* g, uint64_t seed, int32_t nseeds,
