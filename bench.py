@@ -43,7 +43,7 @@ def _log(msg):
 
 
 def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int = 1,
-            solid_height: int | None = None) -> dict:
+            solid_height: int | None = None, over: dict | None = None) -> dict:
     import torch
 
     import paper_1506_01684_amd as pf
@@ -58,7 +58,7 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int
     cells = nx * ny * nz
     pf.set_variant(variant)
     d = pf.Domain(w["shape"], w["prec"])
-    d.set_params(dict(w["params"], shortcuts=shortcuts))
+    d.set_params(dict(w["params"], shortcuts=shortcuts, **(over or {})))
     d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
     _log(f"[bench] {workload}: {nx}x{ny}x{nz} {w['prec']} shortcuts={shortcuts} "
          f"dt={d.dt:.6g} warmup {warmup}")
@@ -79,6 +79,7 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int
         "mlups": cells * steps / wall / 1e6,
         "phi_ms": phi_ms / steps, "mu_ms": mu_ms / steps,
         "nonfinite": diag["nonfinite"], "max_simplex_dev": diag["max_simplex_dev"],
+        "window_shifts": diag["window_shifts"],
     }
     for k in ("phi", "mu"):
         bytes_launch = VALUES_PER_CELL[k] * esize * cells
@@ -106,6 +107,25 @@ def run_scenarios(steps: int, variant: int) -> dict:
                      "phi_ms": round(r1["phi_ms"], 4), "mu_ms": round(r1["mu_ms"], 4),
                      "plain_phi_ms": round(r0["phi_ms"], 4), "plain_mu_ms": round(r0["mu_ms"], 4)}
     return out
+
+
+def run_window(steps: int, variant: int) -> dict:
+    """Moving window on the headline domain: with the window plane far
+    above the front (the per-step check only), and with it below the front
+    so that every timed step starts with a shift (one plane of the whole
+    state copied down)."""
+    import pfinputs
+
+    nz = pfinputs.workload("c2")["shape"][0]
+    chk = run_gpu("c2", steps, 5, variant, 1, over={"window_z": nz - 64})
+    n = min(steps, 48)
+    sh = run_gpu("c2", n, 5, variant, 1, over={"window_z": 64})
+    return {"check_only": {"window_z": nz - 64, "mlups": round(chk["mlups"], 1),
+                           "ms_per_step": round(chk["ms_per_step"], 4),
+                           "shifts": chk["window_shifts"]},
+            "every_step_shifts": {"window_z": 64, "steps": n, "mlups": round(sh["mlups"], 1),
+                                  "ms_per_step": round(sh["ms_per_step"], 4),
+                                  "shifts": sh["window_shifts"]}}
 
 
 def run_stream(nbytes: int = 2 << 30, reps: int = 10) -> dict:
@@ -325,6 +345,8 @@ def main():
     ap.add_argument("--no-fp32-error", action="store_true",
                     help="skip the 1000-step FP32-vs-FP64 error run")
     ap.add_argument("--shortcuts", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--no-window", action="store_true",
+                    help="skip the moving-window timings of the headline domain")
     ap.add_argument("--no-scenarios", action="store_true",
                     help="skip the interface/solid/liquid timings of the headline domain")
     ap.add_argument("--pack-steps", type=int, default=100)
@@ -407,6 +429,9 @@ def main():
     if not args.no_scenarios and args.workload == "c2":
         _log("[bench] interface / solid / liquid scenarios")
         line["scenarios"] = run_scenarios(args.steps // 2, args.variant)
+    if not args.no_window and args.workload == "c2":
+        _log("[bench] moving window")
+        line["window"] = run_window(args.steps // 2, args.variant)
     if not args.no_fp32 and args.workload == "c2":
         r32 = run_gpu("c3", args.fp32_steps, 5, args.variant, args.shortcuts)
         line["fp32"] = {

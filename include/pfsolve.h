@@ -99,6 +99,18 @@ typedef struct {
                          * a pure cell with zero face sums that is a fixed
                          * point of its plane keeps its value.  Results are
                          * bitwise identical to 0 (evaluate everything). */
+  int32_t window_z;     /* moving window along z (Sec. 3.3, the technique of
+                         * Vondrous et al. 2014 the paper cites): 0 = off, else
+                         * a plane index in [1, nz-2].  Before each step, if the
+                         * mean liquid fraction of plane window_z (FP64 sum of
+                         * phi_3 over the plane) is below 1/2, the front has
+                         * passed it: every plane moves down by one (plane 0,
+                         * deep in the solid, is dropped), the top plane becomes
+                         * liquid (phi = e_3) at mu = mu_fill, and the origin of
+                         * z moves up by dx (the temperature uses
+                         * zoff + shifts dx).  At most one shift per step. */
+  int32_t window_reserved; /* must be 0 */
+  double mu_fill[2];    /* mu of the liquid plane a window shift adds */
 } pf_params;
 
 typedef enum { PF_INIT_VORONOI = 0, PF_INIT_HOST = 1 } pf_init_kind;
@@ -122,6 +134,7 @@ typedef struct {
   double max_simplex_dev; /* max over cells of |sum_a phi_a - 1|           */
   double phi_min, phi_max;
   int64_t nonfinite;      /* cells holding a NaN or Inf in any field      */
+  int64_t window_shifts;  /* moving-window shifts since pf_init_fields    */
 } pf_diag;
 
 /* Device bytes a domain needs (both field copies plus scratch). */
@@ -145,7 +158,8 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p);
 /* The resolved time step and the stability bound. */
 pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
 
-/* Initialise both sweeps' source fields; resets the step index to 0.
+/* Initialise both sweeps' source fields; resets the step index and the
+ * window shift count to 0.
  * VORONOI (Sec. 2.1): nseeds points drawn with SplitMix64 (Steele, Lea,
  * Flood 2014) as (u nx, u ny), u = (next >> 11) 2^-53, x first; seed s gets
  * solid phase s mod 3; each column takes the nearest seed by periodic
@@ -154,7 +168,9 @@ pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
  * HOST: copy (and for FP32 round) the caller's arrays.  Synchronises. */
 pf_status pf_init_fields(pf_domain* d, const pf_init* init);
 
-/* Resume from a checkpoint: the next step is number `step`, t = step dt. */
+/* Resume from a checkpoint: the next step is number `step`, t = step dt.
+ * The window shift count is kept; a caller resuming a windowed run from
+ * host fields sets pf_params.zoff to the old zoff plus shifts * dx. */
 pf_status pf_set_time(pf_domain* d, int64_t step);
 
 /* Enqueue n time steps (Algorithm 1), asynchronously.  Errors: STATE when

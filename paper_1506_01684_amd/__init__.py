@@ -98,6 +98,10 @@ def params_struct(p: dict) -> A.PfParams:
     s.mu_frozen = int(p.get("mu_frozen", 0))
     s.diag_every = int(p.get("diag_every", 0))
     s.shortcuts = int(p.get("shortcuts", 1))
+    s.window_z = int(p.get("window_z", 0))
+    s.window_reserved = 0
+    fill = p.get("mu_fill", (0.0, 0.0))
+    s.mu_fill[0], s.mu_fill[1] = float(fill[0]), float(fill[1])
     return s
 
 
@@ -229,6 +233,7 @@ class Domain:
             "t": dg.t, "step": dg.step, "sum_c": list(dg.sum_c), "sum_phi": list(dg.sum_phi),
             "max_simplex_dev": dg.max_simplex_dev, "phi_min": dg.phi_min,
             "phi_max": dg.phi_max, "nonfinite": dg.nonfinite,
+            "window_shifts": dg.window_shifts,
         }
 
 

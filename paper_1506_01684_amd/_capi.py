@@ -42,7 +42,8 @@ class PfParams(C.Structure):
         ("c0", (_D * 2) * 4), ("c1", (_D * 2) * 4), ("w0", _D * 4), ("w1", _D * 4),
         ("D", _D * 4), ("TE", _D), ("T0", _D), ("G", _D), ("v", _D), ("zoff", _D), ("dt", _D),
         ("antitrapping", C.c_int32), ("mu_frozen", C.c_int32), ("diag_every", C.c_int32),
-        ("shortcuts", C.c_int32),
+        ("shortcuts", C.c_int32), ("window_z", C.c_int32), ("window_reserved", C.c_int32),
+        ("mu_fill", _D * 2),
     ]
 
 
@@ -58,6 +59,7 @@ class PfDiag(C.Structure):
     _fields_ = [
         ("t", _D), ("step", C.c_int64), ("sum_c", _D * 2), ("sum_phi", _D * 4),
         ("max_simplex_dev", _D), ("phi_min", _D), ("phi_max", _D), ("nonfinite", C.c_int64),
+        ("window_shifts", C.c_int64),
     ]
 
 

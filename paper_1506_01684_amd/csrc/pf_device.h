@@ -97,6 +97,12 @@ struct DevDomain {
   int32_t cur_src;            // prologue: source copy of the running step
   int64_t cur_step;           // prologue: index of the running step
   int64_t steps_left;         // < 0: unlimited
+  int32_t window_z;           // moving-window plane (0 = off)
+  int32_t shift_now;          // prologue: this step starts with a window shift
+  int64_t shifts;             // window shifts so far (z origin = zoff + shifts dx)
+  int32_t shift_src;          // prologue: copy the shift reads (it writes cur_src)
+  int32_t window_pad;
+  double mu_fill[NM];         // mu of the liquid plane a shift adds
   void* copy[2];              // base of each 6-field copy
   void* coef;                 // PlaneCoef<R>[nz] of the running step
   double dt, dx;

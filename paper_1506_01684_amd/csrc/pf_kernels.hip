@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
   DevDomain& d = *doms[blockIdx.x];
   __shared__ int64_t s_step;
   __shared__ int s_src, s_act;
+  __shared__ double s_red[256];
   if (threadIdx.x == 0) {
     int act = d.steps_left != 0;
     s_act = act;
@@ -43,11 +44,32 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     if (threadIdx.x == 0) d.active = 0;
     return;
   }
+  // Moving window: has the front passed plane window_z?  The liquid
+  // fraction of that plane of the current state is summed in FP64 (strided
+  // per thread, then a fixed tree); below half the plane area the step
+  // starts with a shift, which the window kernel performs by copying the
+  // current copy into the other one, one plane lower.
+  int shift = 0;
+  if (d.window_z > 0) {
+    const R* pl = static_cast<const R*>(d.copy[s_src]) + 3 * d.fstride + (int64_t)d.window_z * d.plane;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < d.nx * d.ny; c += blockDim.x)
+      acc += (double)pl[(int64_t)(c / d.nx) * d.pitch + c % d.nx];
+    s_red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+      __syncthreads();
+    }
+    shift = s_red[0] < 0.5 * (double)d.nx * (double)d.ny;
+  }
+  const int src = shift ? s_src ^ 1 : s_src;
+  const double zoff = d.zoff + (double)(d.shifts + shift) * d.dx;
   const int64_t n = s_step;
   const double t0 = (double)n * d.dt, t1 = (double)(n + 1) * d.dt;
   PlaneCoef<R>* tab = static_cast<PlaneCoef<R>*>(d.coef);
   for (int k = threadIdx.x; k < d.nz; k += blockDim.x) {
-    const double zc = (double)k * d.dx + d.zoff;
+    const double zc = (double)k * d.dx + zoff;
     const double Tn = d.T0 + d.G * (zc - d.v * t0);
     const double Tz = d.T0 + d.G * (zc + 0.5 * d.dx - d.v * t0);
     const double Tn1 = d.T0 + d.G * (zc - d.v * t1);
@@ -109,10 +131,44 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
   if (threadIdx.x == 0) {
     d.active = 1;
     d.cur_step = n;
-    d.cur_src = s_src;
+    d.shift_now = shift;
+    d.shift_src = s_src;
+    d.shifts += shift;
+    d.cur_src = src;
     d.step = n + 1;
-    d.parity = s_src ^ 1;
+    d.parity = src ^ 1;
     if (d.steps_left > 0) d.steps_left -= 1;
+  }
+}
+
+// Window shift of the domains whose prologue decided one: the running
+// source copy (cur_src) receives the state of copy shift_src moved down by
+// one plane, with a liquid plane at mu_fill on top.  Work items are the
+// sweeps' (tile, z chunk) items; each thread copies its column.
+template <typename R>
+__global__ __launch_bounds__(kTileThreads) void window_kernel(DevDomain* const* doms,
+                                                              const int32_t* first, int ndom,
+                                                              int total) {
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int di = find_domain(first, ndom, item);
+    const PF_CONST DevDomain& d = domain_at(doms, di);
+    if (!d.active || !d.shift_now) continue;
+    const WorkTile w = decode_item(d, item - first_item(first, di), threadIdx.x);
+    if (!w.valid) continue;
+    const R* from = static_cast<const R*>(d.copy[d.shift_src]);
+    R* to = static_cast<R*>(d.copy[d.cur_src]);
+    const int64_t col = (int64_t)w.y * d.pitch + w.x;
+    for (int k = w.z0; k < w.z1; ++k) {
+      const bool top = k == d.nz - 1;
+      const int64_t o = (int64_t)k * d.plane + col;
+      const int64_t os = (int64_t)(top ? k : k + 1) * d.plane + col;  // never past plane nz-1
+#pragma unroll
+      for (int f = 0; f < NP + NM; ++f) {
+        const R fill = f < NP ? (f == LQ ? R(1) : R(0)) : (R)d.mu_fill[f - NP];
+        const R v = from[f * d.fstride + os];
+        to[f * d.fstride + o] = top ? fill : v;
+      }
+    }
   }
 }
 
@@ -368,7 +424,7 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const DevDomain* dom,
     }
     v[6] = fmax(v[6], fabs(sum - 1.0));
     v[9] += bad ? 1.0 : 0.0;
-    const double T = d.T0 + d.G * ((double)z * d.dx + d.zoff - d.v * t);
+    const double T = d.T0 + d.G * ((double)z * d.dx + d.zoff + (double)d.shifts * d.dx - d.v * t);
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
       double cq = 0.0;
@@ -417,6 +473,14 @@ hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s) {
     prologue_kernel<double><<<L.ndom, 256, 0, s>>>(L.doms, L.ndom);
   else
     prologue_kernel<float><<<L.ndom, 256, 0, s>>>(L.doms, L.ndom);
+  return hipGetLastError();
+}
+
+hipError_t launch_window(const LaunchSet& L, int prec, hipStream_t s) {
+  if (prec == 0)
+    window_kernel<double><<<L.total, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  else
+    window_kernel<float><<<L.total, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   return hipGetLastError();
 }
 

@@ -300,6 +300,7 @@ pf_status enqueue_step(pf_domain* d, hipEvent_t* ev) {
   const int prec = d->desc.prec;
   const int var = g_variant.load();
   PF_HIP(launch_prologue(s, prec, d->stream));
+  if (d->host.window_z > 0) PF_HIP(launch_window(s, prec, d->stream));
   if (ev) PF_HIP(hipEventRecord(ev[0], d->stream));
   PF_HIP(launch_phi(s, prec, d->aniso, var, d->stream));
   if (ev) PF_HIP(hipEventRecord(ev[1], d->stream));
@@ -429,6 +430,11 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
 pf_status pf_set_params(pf_domain* d, const pf_params* p) {
   if (!d || !p) return fail(PF_ERR_INVALID_ARG, "null argument");
   if (p->diag_every < 0) return fail(PF_ERR_INVALID_ARG, "diag_every must be >= 0");
+  if (p->window_z != 0 && (p->window_z < 1 || p->window_z > d->desc.nz - 2))
+    return fail(PF_ERR_INVALID_ARG, "window_z must be 0 or in [1, nz-2]");
+  if (p->window_reserved != 0) return fail(PF_ERR_INVALID_ARG, "window_reserved must be 0");
+  if (!std::isfinite(p->mu_fill[0]) || !std::isfinite(p->mu_fill[1]))
+    return fail(PF_ERR_INVALID_ARG, "mu_fill must be finite");
   double bound = 0.0;
   pf_status st = validate_and_bound(d, *p, bound);
   if (st != PF_OK) return st;
@@ -448,6 +454,9 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p) {
   h.G = p->G;
   h.v = p->v;
   h.zoff = p->zoff;
+  h.window_z = p->window_z;
+  h.mu_fill[0] = p->mu_fill[0];
+  h.mu_fill[1] = p->mu_fill[1];
   std::memcpy(h.chi0, p->chi0, sizeof(h.chi0));
   std::memcpy(h.chi1, p->chi1, sizeof(h.chi1));
   std::memcpy(h.c0, p->c0, sizeof(h.c0));
@@ -463,6 +472,7 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p) {
     if ((st = fetch_state(d, cur)) != PF_OK) return st;
     h.step = cur.step;
     h.parity = cur.parity;
+    h.shifts = cur.shifts;
   }
   h.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
@@ -496,6 +506,8 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   }
   h.step = 0;
   h.parity = 0;
+  h.shifts = 0;
+  h.shift_now = 0;
   h.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
   if (in->kind == PF_INIT_VORONOI) {
@@ -546,6 +558,7 @@ pf_status pf_set_time(pf_domain* d, int64_t step) {
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
   d->host.step = step;
   d->host.parity = cur.parity;
+  d->host.shifts = cur.shifts;
   d->host.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
   PF_HIP(hipStreamSynchronize(d->stream));
@@ -663,6 +676,7 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->phi_min = v[7];
     diag->phi_max = v[8];
     diag->nonfinite = (int64_t)v[9];
+    diag->window_shifts = cur.shifts;
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
   }
@@ -693,6 +707,7 @@ struct pf_pack {
   int32_t* dev_first = nullptr;
   int32_t total = 0, max_nz = 0;
   bool any_aniso = false;
+  bool any_window = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
@@ -712,11 +727,13 @@ pf_status rebuild_pack(pf_pack* pk) {
   std::vector<DevDomain*> ptrs;
   std::vector<int32_t> first(1, 0);
   pk->any_aniso = false;
+  pk->any_window = false;
   pk->max_nz = 0;
   for (pf_domain* d : pk->members) {
     ptrs.push_back(d->dev);
     first.push_back(first.back() + d->T.blocks());
     pk->any_aniso |= d->aniso;
+    pk->any_window |= d->host.window_z > 0;
     pk->max_nz = std::max(pk->max_nz, d->desc.nz);
   }
   pk->total = first.back();
@@ -738,6 +755,7 @@ pf_status rebuild_pack(pf_pack* pk) {
     const int var = g_variant.load();
     PF_HIP(hipStreamBeginCapture(pk->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_prologue(s, pk->prec, pk->stream);
+    if (e1 == hipSuccess && pk->any_window) e1 = launch_window(s, pk->prec, pk->stream);
     hipError_t e2 = launch_phi(s, pk->prec, pk->any_aniso, var, pk->stream);
     hipError_t e3 = launch_mu(s, pk->prec, var, pk->stream);
     hipError_t e4 = hipStreamEndCapture(pk->stream, &pk->graph);
