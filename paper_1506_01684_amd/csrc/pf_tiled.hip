@@ -464,6 +464,9 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
     const Copy& dst = X.dst;  // phi^{n+1} (written by the phi-sweep), mu^{n+1}
     const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
     const bool antitrap = P.antitrap != 0;
+    // FP64: the three own faces side by side (more independent work per
+    // wave at two waves per SIMD); FP32, held to 128 VGPRs, one at a time
+    constexpr bool ILP = sizeof(R) == 8;
     const int kstart = G.z0 - 1;
 
     if (P.mu_frozen) {  // mu^{n+1} = mu^n (tests of the phi part only)
@@ -521,65 +524,164 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
       if (G.halo_c >= 0) nxt_p1h = load4<R>(dst, k1, G.halo_b);
       const int kk = k < 0 ? 0 : k;
       const auto& C = X.tab[kk];
-      if (cells) {
-        const bool ex = ex_ok && wave == ((k + 1) & 3);
-        const bool ey = ey_ok && wave == (k & 3);
-#pragma unroll 1
-        for (int r = 0; r < 2; ++r) {
-          const bool edge = r == 1;
-          if (edge ? !ex : !G.valid) continue;
-          const int cx = edge ? 0 : G.lx + 1, cy = edge ? lane + 1 : G.ly + 1;
-          const int fo = edge ? lane * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
+      // x face between LDS cells (cx,cy), (cx+1,cy) and y face between
+      // (cx,cy), (cx,cy+1) of plane k, with their anti-trapping terms
+      const auto j_x = [&](int cx, int cy, const R pb[NP], const R gn[NP], const R mL[NM],
+                           const R mU[NM], R Phi[NM]) {
+        R gt1[NP], gt2[NP], dph[3];
+        lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+        face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx + 1, cy)),
+                     s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)), dph);
+        mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+      };
+      const auto j_y = [&](int cx, int cy, const R pb[NP], const R gn[NP], const R mL[NM],
+                           const R mU[NM], R Phi[NM]) {
+        R gt1[NP], gt2[NP], dph[3];
+        lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+        face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx, cy + 1)),
+                     s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)), dph);
+        mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+      };
+      R Pzu[NM] = {R(0), R(0)};  // z face above plane k
+      if constexpr (ILP) {
+        // The three faces above the own cell (x, y, and z above plane k) are
+        // independent: their diffusive parts are evaluated side by side; the
+        // anti-trapping terms follow where needed, re-reading the face values
+        // so that no face's inputs stay live across the others.
+        const bool own = cells && G.valid;
+        const bool zf = k >= 0 && k < g.nz - 1;
+        const int ox = G.lx + 1, oy = G.ly + 1;
+        R Phx[NM], Phy[NM];
+        bool jx = false, jy = false, jz = false;
+        if (own) {
+          R pbx[NP], gnx[NP], pby[NP], gny[NP], mUx[NM], mUy[NM];
+          lds_face_normal<R, 0>(s_phi, G, ox, oy, s0, sp, inv_dx, pbx, gnx);
+          lds_face_normal<R, 1>(s_phi, G, ox, oy, s0, sp, inv_dx, pby, gny);
+          s_mu.get(G.ci(ox + 1, oy), mUx);
+          s_mu.get(G.ci(ox, oy + 1), mUy);
+          mu_face_diff<R, false>(P, C, pbx, ownm, mUx, Phx);
+          mu_face_diff<R, false>(P, C, pby, ownm, mUy, Phy);
+          jx = antitrap && mu_face_needs_j(pbx);
+          jy = antitrap && mu_face_needs_j(pby);
+        }
+        if (zf) {
+          R pbz[NP], gnz[NP];
+          lds_face_normal<R, 2>(s_phi, G, ox, oy, s0, sp, inv_dx, pbz, gnz);
+          mu_face_diff<R, true>(P, C, pbz, ownm, upm, Pzu);
+          jz = antitrap && mu_face_needs_j(pbz);
+        }
+        if (jx) {
+          R pb[NP], gn[NP], mU[NM];
+          lds_face_normal<R, 0>(s_phi, G, ox, oy, s0, sp, inv_dx, pb, gn);
+          s_mu.get(G.ci(ox + 1, oy), mU);
+          j_x(ox, oy, pb, gn, ownm, mU, Phx);
+        }
+        if (jy) {
+          R pb[NP], gn[NP], mU[NM];
+          lds_face_normal<R, 1>(s_phi, G, ox, oy, s0, sp, inv_dx, pb, gn);
+          s_mu.get(G.ci(ox, oy + 1), mU);
+          j_y(ox, oy, pb, gn, ownm, mU, Phy);
+        }
+        if (jz) {
+          R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3];
+          lds_face_normal<R, 2>(s_phi, G, ox, oy, s0, sp, inv_dx, pb, gn);
+          lds_face_tangential<R, 2>(s_phi, G, ox, oy, sm, s0, sp, inv_4dx, gt1, gt2);
+          const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
+  #pragma unroll
+          for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
+          mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+        }
+        if (own) {
+          const int fx = G.ly * (G.tx + 1) + G.lx + 1, fy = (G.ly + 1) * G.tx + G.lx;
+          s_fx[0][fx] = Phx[0];
+          s_fx[1][fx] = Phx[1];
+          s_fy[0][fy] = Phy[0];
+          s_fy[1][fy] = Phy[1];
+        }
+        // the tile's lower-edge faces: lane l of one wave per direction,
+        // rotating with the plane (x edge: wave (k+1) mod 4, y edge: k mod 4)
+        if (cells && ex_ok && wave == ((k + 1) & 3)) {
+          const int cx = 0, cy = lane + 1;
           R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
           lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
           s_mu.get(G.ci(cx, cy), mL);
           s_mu.get(G.ci(cx + 1, cy), mU);
           mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
-          if (antitrap && mu_face_needs_j(pb)) {
-            R gt1[NP], gt2[NP], dph[3];
-            lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
-            face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx + 1, cy)),
-                         s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)), dph);
-            mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
-          }
-          s_fx[0][fo] = Phi[0];
-          s_fx[1][fo] = Phi[1];
+          if (antitrap && mu_face_needs_j(pb)) j_x(cx, cy, pb, gn, mL, mU, Phi);
+          s_fx[0][lane * (G.tx + 1)] = Phi[0];
+          s_fx[1][lane * (G.tx + 1)] = Phi[1];
         }
-#pragma unroll 1
-        for (int r = 0; r < 2; ++r) {
-          const bool edge = r == 1;
-          if (edge ? !ey : !G.valid) continue;
-          const int cx = edge ? lane + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
-          const int fo = edge ? lane : (G.ly + 1) * G.tx + G.lx;
+        if (cells && ey_ok && wave == (k & 3)) {
+          const int cx = lane + 1, cy = 0;
           R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
           lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
           s_mu.get(G.ci(cx, cy), mL);
           s_mu.get(G.ci(cx, cy + 1), mU);
           mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+          if (antitrap && mu_face_needs_j(pb)) j_y(cx, cy, pb, gn, mL, mU, Phi);
+          s_fy[0][lane] = Phi[0];
+          s_fy[1][lane] = Phi[1];
+        }
+      } else {
+        if (cells) {
+          const bool ex = ex_ok && wave == ((k + 1) & 3);
+          const bool ey = ey_ok && wave == (k & 3);
+  #pragma unroll 1
+          for (int r = 0; r < 2; ++r) {
+            const bool edge = r == 1;
+            if (edge ? !ex : !G.valid) continue;
+            const int cx = edge ? 0 : G.lx + 1, cy = edge ? lane + 1 : G.ly + 1;
+            const int fo = edge ? lane * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
+            R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
+            lds_face_normal<R, 0>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
+            s_mu.get(G.ci(cx, cy), mL);
+            s_mu.get(G.ci(cx + 1, cy), mU);
+            mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+            if (antitrap && mu_face_needs_j(pb)) {
+              R gt1[NP], gt2[NP], dph[3];
+              lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+              face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx + 1, cy)),
+                           s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)), dph);
+              mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+            }
+            s_fx[0][fo] = Phi[0];
+            s_fx[1][fo] = Phi[1];
+          }
+  #pragma unroll 1
+          for (int r = 0; r < 2; ++r) {
+            const bool edge = r == 1;
+            if (edge ? !ey : !G.valid) continue;
+            const int cx = edge ? lane + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
+            const int fo = edge ? lane : (G.ly + 1) * G.tx + G.lx;
+            R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
+            lds_face_normal<R, 1>(s_phi, G, cx, cy, s0, sp, inv_dx, pb, gn);
+            s_mu.get(G.ci(cx, cy), mL);
+            s_mu.get(G.ci(cx, cy + 1), mU);
+            mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+            if (antitrap && mu_face_needs_j(pb)) {
+              R gt1[NP], gt2[NP], dph[3];
+              lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+              face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx, cy + 1)),
+                           s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)), dph);
+              mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+            }
+            s_fy[0][fo] = Phi[0];
+            s_fy[1][fo] = Phi[1];
+          }
+        }
+        // z face above plane k
+        if (k >= 0 && k < g.nz - 1) {
+          R pb[NP], gn[NP];
+          lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
+          mu_face_diff<R, true>(P, C, pb, ownm, upm, Pzu);
           if (antitrap && mu_face_needs_j(pb)) {
             R gt1[NP], gt2[NP], dph[3];
-            lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
-            face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx, cy + 1)),
-                         s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)), dph);
-            mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+            lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
+            const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
+  #pragma unroll
+            for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
+            mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
           }
-          s_fy[0][fo] = Phi[0];
-          s_fy[1][fo] = Phi[1];
-        }
-      }
-      // z face above plane k
-      R Pzu[NM] = {R(0), R(0)};
-      if (k >= 0 && k < g.nz - 1) {
-        R pb[NP], gn[NP];
-        lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
-        mu_face_diff<R, true>(P, C, pb, ownm, upm, Pzu);
-        if (antitrap && mu_face_needs_j(pb)) {
-          R gt1[NP], gt2[NP], dph[3];
-          lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
-          const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
-          mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
         }
       }
       V4<R> own0;
