@@ -276,7 +276,8 @@ def run_pack(count: int, steps: int, warmup: int) -> dict:
     }
 
 
-def run_serving(count: int, lateral, steps_rng, rate: float, budget: float, serial: bool) -> dict:
+def run_serving(count: int, lateral, steps_rng, rate: float, budget: float, serial: bool,
+                policies=("fifo", "sjf"), progress: bool = False) -> dict:
     """Poisson arrivals of Voronoi solves of mixed size, step count and
     precision through the continuous-batching server; the serial baseline
     runs the same trace first come, first served with single-domain
@@ -286,16 +287,25 @@ def run_serving(count: int, lateral, steps_rng, rate: float, budget: float, seri
 
     trace = pfinputs.serving_trace(count=count, rate=rate, lateral=lateral, steps=steps_rng)
     reqs = [S.request_from_trace(t) for t in trace]
-    be = S.GpuBackend(max_domains=256)
-    srv = S.Server(be, budget_bytes=budget, max_slots=256, round_steps=25)
-    res = srv.run(reqs)
-    be.shutdown()
     out = {
         "workload": f"{count} requests, Poisson {rate}/s, lateral {lateral[0]}-{lateral[1]}, "
                     f"Nz = 2L, steps {steps_rng[0]}-{steps_rng[1]}, fp32/fp64 half each, "
                     f"budget {budget / 1e9:.0f} GB",
-        "server": S.summarize(res),
     }
+    for pol in policies:
+        _log(f"[bench] serving with policy {pol}")
+        be = S.GpuBackend(max_domains=256)
+        kw = {} if pol == "fifo" else dict(policy="sjf", target_cells=32e6, rate=2e10)
+        srv = S.Server(be, budget_bytes=budget, max_slots=256, round_steps=25,
+                       log=_log if progress else None, **kw)
+        res = srv.run(reqs)
+        be.shutdown()
+        if pol == "fifo":
+            out["server"] = dict(S.summarize(res), policy="arrival order, every request "
+                                                          "admitted that fits")
+        else:
+            out["server_sjf"] = dict(S.summarize(res), policy="shortest expected job first "
+                                                              "with aging, packs held to 32M cells")
     if serial:
         out["serial_fifo"] = S.summarize(S.run_serial_gpu(reqs))
     return out
@@ -354,6 +364,10 @@ def main():
     ap.add_argument("--full-serving", action="store_true",
                     help="only run the full serving trace: 128 requests, lateral 64-384, "
                          "steps 200-5000, 200 GB budget (long)")
+    ap.add_argument("--serve-policy", default="sjf", choices=["fifo", "sjf"],
+                    help="scheduling policy of the --full-serving run")
+    ap.add_argument("--serve-rate", type=float, default=20.0,
+                    help="mean Poisson arrival rate (1/s) of the --full-serving run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times "
                          "(reference for the FETCH_SIZE/WRITE_SIZE counter scale)")
@@ -369,7 +383,8 @@ def main():
         print(json.dumps({"copy_bytes": args.calibrate_copy, "repeats": 5}))
         return
     if args.full_serving:
-        r = run_serving(128, (64, 384), (200, 5000), 20.0, 200e9, serial=False)
+        r = run_serving(128, (64, 384), (200, 5000), args.serve_rate, 200e9, serial=False,
+                        policies=(args.serve_policy,), progress=True)
         print(json.dumps({"metric": "served-solve latency (p50/p99)", "serving": r}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

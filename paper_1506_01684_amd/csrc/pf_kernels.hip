@@ -53,8 +53,20 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
   if (d.window_z > 0) {
     const R* pl = static_cast<const R*>(d.copy[s_src]) + 3 * d.fstride + (int64_t)d.window_z * d.plane;
     double acc = 0.0;
-    for (int c = threadIdx.x; c < d.nx * d.ny; c += blockDim.x)
-      acc += (double)pl[(int64_t)(c / d.nx) * d.pitch + c % d.nx];
+    // rows of the plane over the threads, eight loads in flight per thread
+    const int n = d.nx * d.ny;
+    int c = threadIdx.x;
+    for (; c + 7 * (int)blockDim.x < n; c += 8 * blockDim.x) {
+      R v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int cu = c + u * blockDim.x;
+        v[u] = pl[(int64_t)(cu / d.nx) * d.pitch + cu % d.nx];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; c < n; c += blockDim.x) acc += (double)pl[(int64_t)(c / d.nx) * d.pitch + c % d.nx];
     s_red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -477,10 +489,13 @@ hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s) {
 }
 
 hipError_t launch_window(const LaunchSet& L, int prec, hipStream_t s) {
+  // a shift is rare (the front moves a small fraction of a cell per step),
+  // so the grid is capped: most launches only read each block's flags
+  const int grid = L.total < 1024 ? L.total : 1024;
   if (prec == 0)
-    window_kernel<double><<<L.total, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    window_kernel<double><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   else
-    window_kernel<float><<<L.total, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    window_kernel<float><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   return hipGetLastError();
 }
 

@@ -192,12 +192,25 @@ class Server:
     max_slots: admitted domains at most.
     round_steps: steps each pack advances between scheduling decisions.
     backfill: admit later requests that fit while the queue head does not.
+    policy: "fifo" admits in arrival order; "sjf" admits the request with
+        the least expected service time minus time already waited (shortest
+        job first with aging, so that long jobs are not starved).
+    target_cells: with a value, a pack admits a request only while its
+        members hold fewer cells than this (one request is always admitted
+        into an empty pack): beyond the cells that fill the device, more
+        members only stretch every member's latency.
+    rate: assumed throughput (cells x steps per second) for the "sjf"
+        service-time estimate; FP64 work counts twice.
     """
 
     def __init__(self, backend, budget_bytes: float = 200e9, max_slots: int = 64,
                  round_steps: int = 25, backfill: bool = True,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep,
+                 policy: str = "fifo", target_cells: float | None = None,
+                 rate: float = 2e10, log: Callable[[str], None] | None = None):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError(f"unknown policy {policy!r}")
         self.b = backend
         self.budget = budget_bytes
         self.max_slots = max_slots
@@ -205,7 +218,14 @@ class Server:
         self.backfill = backfill
         self.clock = clock
         self.sleep = sleep
+        self.policy = policy
+        self.target_cells = target_cells
+        self.rate = rate
+        self.log = log
         self.events: list[tuple] = []
+
+    def _service(self, r: Request) -> float:
+        return float(np.prod(r.shape)) * r.steps * (2.0 if r.prec == "fp64" else 1.0) / self.rate
 
     def run(self, requests: list[Request]) -> list[Result]:
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.id)))
@@ -222,11 +242,21 @@ class Server:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            # admission in arrival order; with backfill, later requests that
-            # fit may pass a head request that does not
-            for r in list(queue):
+            # admission in arrival order (or, with "sjf", by expected service
+            # time minus time waited); with backfill, later requests that fit
+            # may pass a head request that does not
+            order = list(queue)
+            if self.policy == "sjf":
+                order.sort(key=lambda q: (self._service(q) - (now - q.arrival), q.arrival, q.id))
+            cells = {"fp32": 0, "fp64": 0}
+            for a in active.values():
+                cells[a[0].prec] += int(np.prod(a[0].shape))
+            for r in order:
                 need = self.b.required_bytes(r)
-                if len(active) < self.max_slots and used + need <= self.budget:
+                c = int(np.prod(r.shape))
+                room = (self.target_cells is None or cells[r.prec] == 0
+                        or cells[r.prec] + c <= self.target_cells)
+                if len(active) < self.max_slots and used + need <= self.budget and room:
                     queue.remove(r)
                     try:
                         self.b.open(r)
@@ -237,6 +267,7 @@ class Server:
                         continue
                     active[r.id] = [r, now, need, r.steps]
                     used += need
+                    cells[r.prec] += c
                     self.events.append(("admit", r.id, now, used))
                 elif not self.backfill:
                     break
@@ -267,6 +298,9 @@ class Server:
                 results.append(Result(r.id, r.arrival, adm, fin, int(np.prod(r.shape)),
                                       r.steps, r.prec, not err, err, diag, fields))
                 self.events.append(("finish", r.id, fin, used))
+                if self.log:
+                    self.log(f"[serve] t={fin:.1f}s finished request {r.id} "
+                             f"({len(results)}/{len(requests)}, latency {fin - r.arrival:.2f}s)")
         return sorted(results, key=lambda x: x.id)
 
 

@@ -93,3 +93,39 @@ def test_oversized_request_is_rejected_up_front():
     r = Request(0, 0.0, (512, 512, 512), "fp64", 10, p, 1, 4, 4)
     with pytest.raises(ValueError):
         _run([r], budget_bytes=1e6)
+
+
+def test_sjf_with_cell_target_lowers_median_latency():
+    """A burst of requests whose work spans two orders of magnitude: running
+    everything at once (processor sharing) makes every request wait for the
+    whole burst; admitting the shortest expected jobs first into a pack
+    held near the cells that fill the device lets short jobs leave early."""
+    reqs = _trace(60, rate=200.0)
+    kw = dict(budget_bytes=1e12, max_slots=256, round_steps=10)
+    _, _, fifo = _run(reqs, **kw)
+    _, _, sjf = _run(reqs, policy="sjf", target_cells=2e5, **kw)
+    f, j = summarize(fifo), summarize(sjf)
+    assert j["failed"] == 0 and len(sjf) == len(reqs)
+    assert j["p50_latency_s"] < 0.7 * f["p50_latency_s"]
+    assert j["mean_latency_s"] < f["mean_latency_s"]
+
+
+def test_sjf_ages_long_jobs_in():
+    """A long job arriving first is not starved by a steady stream of short
+    ones: its priority improves with the time it has waited."""
+    p = pfinputs.p0_params(solid_height=4)
+    long_job = Request(0, 0.0, (32, 32, 32), "fp32", 500, p, 1, 4, 4)
+    # short jobs (0.4 ms of service each) arrive every 0.2 ms: without aging
+    # the long job (33 ms) would wait until the stream has drained
+    short = [Request(1 + i, 0.0002 * i, (16, 16, 16), "fp32", 50, p, 1, 4, 4) for i in range(600)]
+    s, b, res = _run([long_job] + short, budget_bytes=1e12, max_slots=256, round_steps=10,
+                     policy="sjf", target_cells=4096)
+    by_id = {r.id: r for r in res}
+    assert all(r.ok for r in res)
+    last_short = max(r.finished for r in res if r.id != 0)
+    assert by_id[0].finished < 0.5 * last_short
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        Server(SimBackend(VirtualClock()), policy="lifo")
