@@ -331,10 +331,20 @@ def run_cpu_baseline(workload: str, budget_s: float = 20.0) -> dict:
         el = time.perf_counter() - t0
         if el * (n + 1) / n > budget_s:
             break
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": cells * n / el / 1e6, "unit": "MLUP/s", "cores": threads, "kind": "oracle",
         "sample": f"{n} full step(s) of the {shape[2]}x{shape[1]}x{shape[0]} FP64 domain "
                   f"from its Voronoi state, z planes split over {threads} threads, {el:.1f} s",
+        "host": {"cpu": cpu, "nproc": os.cpu_count()},
     }
 
 

@@ -51,6 +51,9 @@ struct KParams {
   R g2[NPAIR];     // 2 gamma_ab
   R g16[NPAIR];    // 16/pi^2 gamma_ab (pair part of d omega / d phi)
   R delta[NPAIR];  // cubic anisotropy strength
+  R ac0[NPAIR];    // 1 - 3 delta
+  R d4[NPAIR];     // 4 delta
+  R d16[NPAIR];    // 16 delta
   R gamma3;        // triple coefficient
   R rate[NP];      // dt / (tau_a eps)
   R inv_dx, inv_4dx;
@@ -146,21 +149,26 @@ __device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x)
 
 // Cubic-anisotropic pair term: X = d(ac(q)^2 |q|^2)/dq
 //   = 2 ac [ ac q + 16 delta |q| (qhat^3 - P qhat) ],  P = sum qhat_i^4,
-// with X = 2 q when delta = 0 or |q|^2 <= 1e-30.  Only the component along
-// the face normal D is needed.
+// with X = 2 q when |q|^2 <= 1e-30.  Only the component along the face
+// normal D is needed; with u_i = q_i^2 / |q|^2 (so P = sum u_i^2) it is
+//   X.e_D = 2 ac q_D [ ac + 16 delta (u_D - P) ],  ac = (1 - 3 delta) + 4 delta P,
+// which needs one reciprocal and no square root, and every u_i <= 1 keeps
+// the FP32 evaluation in range.  ac0 = 1 - 3 delta, d4 = 4 delta,
+// d16 = 16 delta.
 template <typename R, int D>
-__device__ __forceinline__ R aniso_Xd(R qx, R qy, R qz, R delta) {
-  const R q[3] = {qx, qy, qz};
-  R qq = qx * qx + qy * qy + qz * qz;
-  if (qq <= R(1e-30)) return R(2) * q[D];
-  R inv = rsq_(qq);
-  R qn = qq * inv;
-  R hx = qx * inv, hy = qy * inv, hz = qz * inv;
-  R P = (hx * hx) * (hx * hx) + (hy * hy) * (hy * hy) + (hz * hz) * (hz * hz);
-  R ac = R(1) - delta * (R(3) - R(4) * P);
-  const R h[3] = {hx, hy, hz};
-  R hd = h[D];
-  return R(2) * ac * (ac * q[D] + R(16) * delta * qn * (hd * hd * hd - P * hd));
+__device__ __forceinline__ R aniso_Xd(R qx, R qy, R qz, R ac0, R d4, R d16) {
+  const R x2 = qx * qx, y2 = qy * qy, z2 = qz * qz;
+  const R qq = x2 + y2 + z2;
+  const R r = rcp_(qq > R(1e-30) ? qq : R(1));
+  const R ux = x2 * r, uy = y2 * r, uz = z2 * r;
+  const R P = ux * ux + uy * uy + uz * uz;
+  const R ac = ac0 + d4 * P;
+  const R qd = D == 0 ? qx : (D == 1 ? qy : qz);
+  const R ud = D == 0 ? ux : (D == 1 ? uy : uz);
+  const R X = R(2) * ac * qd * (ac + d16 * (ud - P));
+  // branch-free guard: with the exact shortcuts most faces reaching here
+  // are interface faces, where a branch would only add mask handling
+  return qq > R(1e-30) ? X : R(2) * qd;
 }
 
 // Face stage of the phi-sweep on a face with normal D.
@@ -190,7 +198,7 @@ __device__ __forceinline__ void phi_face(const KP& P, const R pb[NP], const R gn
         if constexpr (D == 0) { qx = qn; qy = q1; qz = q2; }
         else if constexpr (D == 1) { qx = q1; qy = qn; qz = q2; }
         else { qx = q1; qy = q2; qz = qn; }
-        Y = (R)P.g1[pi] * aniso_Xd<R, D>(qx, qy, qz, (R)P.delta[pi]);
+        Y = (R)P.g1[pi] * aniso_Xd<R, D>(qx, qy, qz, (R)P.ac0[pi], (R)P.d4[pi], (R)P.d16[pi]);
       } else {
         Y = (R)P.g2[pi] * (pb[a] * gn[b] - pb[b] * gn[a]);
       }

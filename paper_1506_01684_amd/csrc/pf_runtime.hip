@@ -276,6 +276,9 @@ void fill_kparams(KParams<R>& k, const pf_params& p, double dt, double dx, bool 
       k.g2[i] = (R)(2.0 * p.gamma[a][b]);
       k.g16[i] = (R)(16.0 / (pi * pi) * p.gamma[a][b]);
       k.delta[i] = (R)p.aniso_delta[a][b];
+      k.ac0[i] = (R)(1.0 - 3.0 * p.aniso_delta[a][b]);
+      k.d4[i] = (R)(4.0 * p.aniso_delta[a][b]);
+      k.d16[i] = (R)(16.0 * p.aniso_delta[a][b]);
     }
   k.gamma3 = (R)p.gamma3;
   for (int a = 0; a < NP; ++a) k.rate[a] = (R)(dt / (p.tau[a] * p.eps));
