@@ -1,0 +1,41 @@
+"""Host-side pieces of bench.py: the device-source digest that guards the
+recorded counter traffic, and the parsing of the committed summary."""
+import json
+import os
+import shutil
+
+import bench
+
+
+def _fake_root(tmp_path, digest):
+    root = tmp_path / "repo"
+    shutil.copytree(os.path.join(bench.ROOT, "paper_1506_01684_amd", "csrc"),
+                    root / "paper_1506_01684_amd" / "csrc")
+    (root / "profiles").mkdir()
+    rec = {"kernel_source_sha256": digest, "fetch_scale": 2.0, "write_scale": 1.0,
+           "kernels": {"c2": {"mu_tiled_f64": {"fetch_kib": 100.0, "write_kib": 50.0}}}}
+    (root / "profiles" / "hbm_traffic.md").write_text(
+        "# HBM traffic\n\ntext\n\n```json\n" + json.dumps(rec) + "\n```\n")
+    return root
+
+
+def test_traffic_is_used_only_for_matching_sources(tmp_path, monkeypatch):
+    digest = bench.kernel_source_digest()
+    root = _fake_root(tmp_path, digest)
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.kernel_source_digest() == digest
+    assert bench.recorded_traffic("mu_tiled_f64", "c2") == (100.0 * 2.0 + 50.0) * 1024.0
+    assert bench.recorded_traffic("phi_tiled_kernel<double, false>", "c2") is None
+    # a changed device source invalidates the record
+    src = root / "paper_1506_01684_amd" / "csrc" / "pf_tiled.hip"
+    src.write_text(src.read_text() + "\n// changed\n")
+    assert bench.kernel_source_digest() != digest
+    assert bench.recorded_traffic("mu_tiled_f64", "c2") is None
+
+
+def test_committed_summary_parses():
+    path = os.path.join(bench.ROOT, "profiles", "hbm_traffic.md")
+    text = open(path).read()
+    rec = json.loads(text.split("```json\n", 1)[1].split("\n```", 1)[0])
+    assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
+    assert "c2" in rec["kernels"] and "c3" in rec["kernels"]
