@@ -34,6 +34,7 @@ class OrcParams(C.Structure):
         ("c0", (_D * 2) * 4), ("c1", (_D * 2) * 4), ("w0", _D * 4), ("w1", _D * 4),
         ("D", _D * 4), ("TE", _D), ("T0", _D), ("G", _D), ("v", _D), ("zoff", _D),
         ("dt", _D), ("antitrapping", C.c_int32), ("mu_frozen", C.c_int32),
+        ("top_dirichlet", C.c_int32), ("pad", C.c_int32), ("mu_top", _D * 2),
     ]
 
 
@@ -109,6 +110,9 @@ def make_params(p: dict) -> OrcParams:
         setattr(s, k, p[k])
     s.antitrapping = int(p.get("antitrapping", 1))
     s.mu_frozen = int(p.get("mu_frozen", 0))
+    s.top_dirichlet = int(p.get("top_bc", 0))
+    fill = p.get("mu_fill", (0.0, 0.0))
+    s.mu_top[0], s.mu_top[1] = float(fill[0]), float(fill[1])
     return s
 
 

@@ -484,8 +484,58 @@ void orc_mu_sweep(const orc_grid* g, const orc_params* p, double t0, double t1,
       }
 }
 
+static void set_ghost_plane(const orc_grid* ge, const orc_params* p, double* phi,
+                            double* mu) {
+  const size_t plane = (size_t)ge->nx * ge->ny, n = ncells(ge);
+  const size_t top = plane * (size_t)(ge->nz - 1);
+  for (size_t c = 0; c < plane; ++c) {
+    for (int a = 0; a < NP; ++a) phi[(size_t)a * n + top + c] = a == ORC_LIQ ? 1.0 : 0.0;
+    if (mu)
+      for (int q = 0; q < NM; ++q) mu[(size_t)q * n + top + c] = p->mu_top[q];
+  }
+}
+
+/* Dirichlet top: copy the fields into a grid one plane taller whose top
+ * plane is the ghost, step there, copy planes 0..nz-1 back. */
+static int run_dirichlet(const orc_grid* g, const orc_params* p, int64_t step0,
+                         int64_t nsteps, double* phi, double* mu, int nthreads) {
+  orc_grid ge = *g;
+  ge.nz = g->nz + 1;
+  const size_t n = ncells(g), ne = ncells(&ge);
+  double* pe = (double*)malloc(sizeof(double) * NP * ne);
+  double* me = (double*)malloc(sizeof(double) * NM * ne);
+  double* pe2 = (double*)malloc(sizeof(double) * NP * ne);
+  double* me2 = (double*)malloc(sizeof(double) * NM * ne);
+  if (!pe || !me || !pe2 || !me2) {
+    free(pe);
+    free(me);
+    free(pe2);
+    free(me2);
+    return -1;
+  }
+  for (int a = 0; a < NP; ++a) memcpy(pe + (size_t)a * ne, phi + (size_t)a * n, sizeof(double) * n);
+  for (int q = 0; q < NM; ++q) memcpy(me + (size_t)q * ne, mu + (size_t)q * n, sizeof(double) * n);
+  for (int64_t s = step0; s < step0 + nsteps; ++s) {
+    double t0 = (double)s * p->dt, t1 = (double)(s + 1) * p->dt;
+    set_ghost_plane(&ge, p, pe, me);
+    orc_phi_sweep(&ge, p, t0, pe, me, pe2, nthreads);
+    set_ghost_plane(&ge, p, pe2, NULL);
+    orc_mu_sweep(&ge, p, t0, t1, pe, pe2, me, me2, nthreads);
+    memcpy(pe, pe2, sizeof(double) * NP * ne);
+    memcpy(me, me2, sizeof(double) * NM * ne);
+  }
+  for (int a = 0; a < NP; ++a) memcpy(phi + (size_t)a * n, pe + (size_t)a * ne, sizeof(double) * n);
+  for (int q = 0; q < NM; ++q) memcpy(mu + (size_t)q * n, me + (size_t)q * ne, sizeof(double) * n);
+  free(pe);
+  free(me);
+  free(pe2);
+  free(me2);
+  return 0;
+}
+
 int orc_run(const orc_grid* g, const orc_params* p, int64_t step0,
             int64_t nsteps, double* phi, double* mu, int nthreads) {
+  if (p->top_dirichlet) return run_dirichlet(g, p, step0, nsteps, phi, mu, nthreads);
   const size_t n = ncells(g);
   double* phi2 = (double*)malloc(sizeof(double) * NP * n);
   double* mu2 = (double*)malloc(sizeof(double) * NM * n);

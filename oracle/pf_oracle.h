@@ -43,6 +43,11 @@ typedef struct {
   double dt;
   int32_t antitrapping;    /* 1: include the anti-trapping current      */
   int32_t mu_frozen;       /* 1: mu is not evolved (tests only)        */
+  int32_t top_dirichlet;   /* 1: Dirichlet top (ghost plane above the top
+                            * is liquid, phi = e_liquid, at mu = mu_top);
+                            * 0: zero-flux mirror, as at the bottom      */
+  int32_t pad;
+  double mu_top[2];
 } orc_params;
 
 typedef struct {
@@ -106,7 +111,11 @@ void orc_mu_sweep(const orc_grid* g, const orc_params* p, double t0, double t1,
                   const double* phi0, const double* phi1, const double* mu,
                   double* mu_out, int nthreads);
 
-/* nsteps full time steps starting at step index step0, in place. */
+/* nsteps full time steps starting at step index step0, in place.  With a
+ * Dirichlet top the sweeps run on the grid extended by the ghost plane
+ * (index nz, held at its fixed values before each sweep), so the face
+ * between the top plane and the ghost is evaluated like any interior face;
+ * only planes 0..nz-1 are kept. */
 int orc_run(const orc_grid* g, const orc_params* p, int64_t step0,
             int64_t nsteps, double* phi, double* mu, int nthreads);
 
