@@ -109,8 +109,13 @@ typedef struct {
                          * liquid (phi = e_3) at mu = mu_fill, and the origin of
                          * z moves up by dx (the temperature uses
                          * zoff + shifts dx).  At most one shift per step. */
-  int32_t window_reserved; /* must be 0 */
-  double mu_fill[2];    /* mu of the liquid plane a window shift adds */
+  int32_t top_bc;       /* top boundary (Sec. 3.1 boundary handling): 0 =
+                         * zero-flux mirror, as at the bottom; 1 = Dirichlet:
+                         * a ghost plane above the top plane is held at
+                         * liquid (phi = e_3) at mu = mu_fill, and the face to
+                         * it is evaluated like any interior face */
+  double mu_fill[2];    /* mu of the liquid a window shift adds and of the
+                         * Dirichlet ghost plane */
 } pf_params;
 
 typedef enum { PF_INIT_VORONOI = 0, PF_INIT_HOST = 1 } pf_init_kind;
@@ -137,7 +142,8 @@ typedef struct {
   int64_t window_shifts;  /* moving-window shifts since pf_init_fields    */
 } pf_diag;
 
-/* Device bytes a domain needs (both field copies plus scratch). */
+/* Device bytes a domain needs (both field copies, each with one extra
+ * plane per field for the Dirichlet ghost, plus scratch). */
 pf_status pf_required_bytes(const pf_domain_desc* desc, size_t* out);
 
 /* Create a domain on the current HIP device.  borrowed: NULL = allocate.

@@ -99,7 +99,7 @@ def params_struct(p: dict) -> A.PfParams:
     s.diag_every = int(p.get("diag_every", 0))
     s.shortcuts = int(p.get("shortcuts", 1))
     s.window_z = int(p.get("window_z", 0))
-    s.window_reserved = 0
+    s.top_bc = int(p.get("top_bc", 0))
     fill = p.get("mu_fill", (0.0, 0.0))
     s.mu_fill[0], s.mu_fill[1] = float(fill[0]), float(fill[1])
     return s

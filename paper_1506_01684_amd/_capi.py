@@ -42,7 +42,7 @@ class PfParams(C.Structure):
         ("c0", (_D * 2) * 4), ("c1", (_D * 2) * 4), ("w0", _D * 4), ("w1", _D * 4),
         ("D", _D * 4), ("TE", _D), ("T0", _D), ("G", _D), ("v", _D), ("zoff", _D), ("dt", _D),
         ("antitrapping", C.c_int32), ("mu_frozen", C.c_int32), ("diag_every", C.c_int32),
-        ("shortcuts", C.c_int32), ("window_z", C.c_int32), ("window_reserved", C.c_int32),
+        ("shortcuts", C.c_int32), ("window_z", C.c_int32), ("top_bc", C.c_int32),
         ("mu_fill", _D * 2),
     ]
 

@@ -104,8 +104,8 @@ struct DevDomain {
   int32_t shift_now;          // prologue: this step starts with a window shift
   int64_t shifts;             // window shifts so far (z origin = zoff + shifts dx)
   int32_t shift_src;          // prologue: copy the shift reads (it writes cur_src)
-  int32_t window_pad;
-  double mu_fill[NM];         // mu of the liquid plane a shift adds
+  int32_t top_bc;             // 1: Dirichlet top (ghost plane nz held at liquid, mu_fill)
+  double mu_fill[NM];         // mu of the liquid plane a shift adds / of the ghost plane
   void* copy[2];              // base of each 6-field copy
   void* coef;                 // PlaneCoef<R>[nz] of the running step
   double dt, dx;

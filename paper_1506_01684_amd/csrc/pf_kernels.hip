@@ -236,7 +236,7 @@ template <typename R, bool ANISO, int D, typename KP>
 __device__ __forceinline__ void phi_face_at(const KP& P, const PF_GLOBAL R* const* f,
                                             const Geo& g, int xl, int yl, int zl, R F[NP],
                                             R S[NP]) {
-  if (D == 2 && (zl < 0 || zl >= g.nz - 1)) {  // zero-flux z boundary
+  if (D == 2 && !g.zface(zl)) {  // zero-flux z boundary
 #pragma unroll
     for (int a = 0; a < NP; ++a) F[a] = S[a] = R(0);
     return;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void mu_face_at(const KP& P, const CP& C, const PF_GL
                                            const PF_GLOBAL R* const* f1,
                                            const PF_GLOBAL R* const* mu, const Geo& g, int xl,
                                            int yl, int zl, R Phi[NM]) {
-  if (D == 2 && (zl < 0 || zl >= g.nz - 1)) {
+  if (D == 2 && !g.zface(zl)) {
     Phi[0] = Phi[1] = R(0);
     return;
   }
@@ -395,6 +395,24 @@ __global__ __launch_bounds__(256) void fill_kernel(const DevDomain* dom, const i
     for (int a = 0; a < NP; ++a) base[a * d.fstride + o] = a == ph ? R(1) : R(0);
     base[4 * d.fstride + o] = (R)mu0;
     base[5 * d.fstride + o] = (R)mu1;
+  }
+}
+
+// Ghost plane nz of both copies for a Dirichlet top: liquid at mu_fill.
+template <typename R>
+__global__ __launch_bounds__(256) void ghost_kernel(const DevDomain* dom) {
+  const DevDomain& d = *dom;
+  const int64_t cols = (int64_t)d.nx * d.ny;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cols;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = (int64_t)d.nz * d.plane + (c / d.nx) * d.pitch + c % d.nx;
+    for (int cp = 0; cp < 2; ++cp) {
+      R* base = static_cast<R*>(d.copy[cp]);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) base[a * d.fstride + o] = a == LQ ? R(1) : R(0);
+      base[4 * d.fstride + o] = (R)d.mu_fill[0];
+      base[5 * d.fstride + o] = (R)d.mu_fill[1];
+    }
   }
 }
 
@@ -544,6 +562,16 @@ hipError_t launch_fill(const DevDomain* dom, int prec, int nx, int ny, int nz,
     fill_kernel<double><<<(int)blocks, 256, 0, s>>>(dom, phase_map, solid_height, mu0, mu1);
   else
     fill_kernel<float><<<(int)blocks, 256, 0, s>>>(dom, phase_map, solid_height, mu0, mu1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost(const DevDomain* dom, int prec, int nx, int ny, hipStream_t s) {
+  const int64_t cols = (int64_t)nx * ny;
+  const int blocks = (int)((cols + 255) / 256 < 1024 ? (cols + 255) / 256 : 1024);
+  if (prec == 0)
+    ghost_kernel<double><<<blocks, 256, 0, s>>>(dom);
+  else
+    ghost_kernel<float><<<blocks, 256, 0, s>>>(dom);
   return hipGetLastError();
 }
 

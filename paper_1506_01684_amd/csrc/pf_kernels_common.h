@@ -10,19 +10,23 @@ namespace pfk {
 
 // Grid geometry with the boundary rules of the model: periodic in x and y,
 // zero-gradient mirror of one ghost layer in z (Sec. 2.1 boundary handling,
-// applied here by index arithmetic instead of ghost cells).
+// applied here by index arithmetic instead of ghost cells).  With a
+// Dirichlet top, plane nz is a stored ghost plane (liquid at a fixed mu):
+// nzr = nz + 1 planes can be read and the face above plane nz-1 exists.
 struct Geo {
-  int nx, ny, nz, pitch;
+  int nx, ny, nz, nzr, pitch;
   int64_t plane;
   __device__ __forceinline__ int xp(int x) const { return x + 1 == nx ? 0 : x + 1; }
   __device__ __forceinline__ int xm(int x) const { return x == 0 ? nx - 1 : x - 1; }
   __device__ __forceinline__ int yp(int y) const { return y + 1 == ny ? 0 : y + 1; }
   __device__ __forceinline__ int ym(int y) const { return y == 0 ? ny - 1 : y - 1; }
-  __device__ __forceinline__ int zp(int z) const { return z + 1 >= nz ? nz - 1 : z + 1; }
+  __device__ __forceinline__ int zp(int z) const { return z + 1 >= nzr ? nzr - 1 : z + 1; }
   __device__ __forceinline__ int zm(int z) const { return z <= 0 ? 0 : z - 1; }
   // plane p with one mirrored ghost plane on each side: -1 -> 0, nz -> nz-1
   // (planes further out are clamped too; they are loaded but never used)
-  __device__ __forceinline__ int zc(int p) const { return p < 0 ? 0 : (p >= nz ? nz - 1 : p); }
+  __device__ __forceinline__ int zc(int p) const { return p < 0 ? 0 : (p >= nzr ? nzr - 1 : p); }
+  // a z face lies above plane k (faces on the mirror boundaries carry no flux)
+  __device__ __forceinline__ bool zface(int k) const { return k >= 0 && k < nzr - 1; }
   __device__ __forceinline__ int64_t at(int x, int y, int z) const {
     return (int64_t)z * plane + (int64_t)y * pitch + x;
   }
@@ -34,6 +38,7 @@ __device__ __forceinline__ Geo make_geo(const DD& d) {
   g.nx = d.nx;
   g.ny = d.ny;
   g.nz = d.nz;
+  g.nzr = d.nz + (d.top_bc ? 1 : 0);
   g.pitch = d.pitch;
   g.plane = d.plane;
   return g;

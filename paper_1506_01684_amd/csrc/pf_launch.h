@@ -24,6 +24,7 @@ constexpr int kTileThreads = 256;
 
 hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s);
 hipError_t launch_window(const LaunchSet& L, int prec, hipStream_t s);
+hipError_t launch_ghost(const DevDomain* dom, int prec, int nx, int ny, hipStream_t s);
 hipError_t launch_phi(const LaunchSet& L, int prec, bool aniso, int variant, hipStream_t s);
 hipError_t launch_mu(const LaunchSet& L, int prec, int variant, hipStream_t s);
 

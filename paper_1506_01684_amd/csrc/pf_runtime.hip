@@ -65,8 +65,9 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   if (cells * L.elem * 12 > (long double)(1ull << 62)) return false;
   L.plane = pitch * (int64_t)d.ny;
   // fields start 4 KiB apart plus a 2 KiB skew, so that equal offsets in
-  // different fields do not fall on the same memory channel
-  const int64_t fe = L.plane * (int64_t)d.nz;
+  // different fields do not fall on the same memory channel; each field has
+  // nz + 1 planes, the last being the ghost plane of a Dirichlet top
+  const int64_t fe = L.plane * ((int64_t)d.nz + 1);
   const int64_t a4k = 4096 / (int64_t)L.elem, skew = 2048 / (int64_t)L.elem;
   L.fstride = (fe + a4k - 1) / a4k * a4k + skew;
   size_t off = 0;
@@ -435,7 +436,7 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p) {
   if (p->diag_every < 0) return fail(PF_ERR_INVALID_ARG, "diag_every must be >= 0");
   if (p->window_z != 0 && (p->window_z < 1 || p->window_z > d->desc.nz - 2))
     return fail(PF_ERR_INVALID_ARG, "window_z must be 0 or in [1, nz-2]");
-  if (p->window_reserved != 0) return fail(PF_ERR_INVALID_ARG, "window_reserved must be 0");
+  if (p->top_bc != 0 && p->top_bc != 1) return fail(PF_ERR_INVALID_ARG, "top_bc must be 0 or 1");
   if (!std::isfinite(p->mu_fill[0]) || !std::isfinite(p->mu_fill[1]))
     return fail(PF_ERR_INVALID_ARG, "mu_fill must be finite");
   double bound = 0.0;
@@ -458,6 +459,7 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p) {
   h.v = p->v;
   h.zoff = p->zoff;
   h.window_z = p->window_z;
+  h.top_bc = p->top_bc;
   h.mu_fill[0] = p->mu_fill[0];
   h.mu_fill[1] = p->mu_fill[1];
   std::memcpy(h.chi0, p->chi0, sizeof(h.chi0));
@@ -479,6 +481,7 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p) {
   }
   h.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
+  if (h.top_bc) PF_HIP(launch_ghost(d->dev, d->desc.prec, d->desc.nx, d->desc.ny, d->stream));
   PF_HIP(hipStreamSynchronize(d->stream));
   d->dt = dt;
   d->bound = bound;
@@ -546,6 +549,10 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
     PF_HIP(hipStreamSynchronize(d->stream));
   } else {
     return fail(PF_ERR_INVALID_ARG, "unknown init kind");
+  }
+  if (h.top_bc) {
+    PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
+    PF_HIP(hipStreamSynchronize(d->stream));
   }
   d->fields_set = true;
   d->since_diag = 0;

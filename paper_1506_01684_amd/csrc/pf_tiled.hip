@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       }
       // z face above plane k (zero on the z boundaries)
       R Fzu[NP] = {}, Szu[NP] = {};
-      if (k >= 0 && k < g.nz - 1) {
+      if (g.zface(k)) {
         R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {};
         if constexpr (ANISO) {
           lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
@@ -529,18 +529,22 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
       const auto j_x = [&](int cx, int cy, const R pb[NP], const R gn[NP], const R mL[NM],
                            const R mU[NM], R Phi[NM]) {
         R gt1[NP], gt2[NP], dph[3];
-        lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
         face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx + 1, cy)),
                      s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)), dph);
-        mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+        {
+          lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+          mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+        }
       };
       const auto j_y = [&](int cx, int cy, const R pb[NP], const R gn[NP], const R mL[NM],
                            const R mU[NM], R Phi[NM]) {
         R gt1[NP], gt2[NP], dph[3];
-        lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
         face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx, cy + 1)),
                      s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)), dph);
-        mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+        {
+          lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+          mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+        }
       };
       R Pzu[NM] = {R(0), R(0)};  // z face above plane k
       if constexpr (ILP) {
@@ -549,7 +553,7 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
         // anti-trapping terms follow where needed, re-reading the face values
         // so that no face's inputs stay live across the others.
         const bool own = cells && G.valid;
-        const bool zf = k >= 0 && k < g.nz - 1;
+        const bool zf = g.zface(k);
         const int ox = G.lx + 1, oy = G.ly + 1;
         R Phx[NM], Phy[NM];
         bool jx = false, jy = false, jz = false;
@@ -585,11 +589,13 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
         if (jz) {
           R pb[NP], gn[NP], gt1[NP], gt2[NP], dph[3];
           lds_face_normal<R, 2>(s_phi, G, ox, oy, s0, sp, inv_dx, pb, gn);
-          lds_face_tangential<R, 2>(s_phi, G, ox, oy, sm, s0, sp, inv_4dx, gt1, gt2);
           const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
   #pragma unroll
           for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
-          mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+          {
+            lds_face_tangential<R, 2>(s_phi, G, ox, oy, sm, s0, sp, inv_4dx, gt1, gt2);
+            mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+          }
         }
         if (own) {
           const int fx = G.ly * (G.tx + 1) + G.lx + 1, fy = (G.ly + 1) * G.tx + G.lx;
@@ -639,10 +645,12 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
             mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
             if (antitrap && mu_face_needs_j(pb)) {
               R gt1[NP], gt2[NP], dph[3];
-              lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
               face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx + 1, cy)),
                            s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx + 1, cy)), dph);
-              mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+              {
+                lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+                mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+              }
             }
             s_fx[0][fo] = Phi[0];
             s_fx[1][fo] = Phi[1];
@@ -660,27 +668,31 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
             mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
             if (antitrap && mu_face_needs_j(pb)) {
               R gt1[NP], gt2[NP], dph[3];
-              lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
               face_dphi<R>(s_p1.get(0, G.ci(cx, cy)), s_p1.get(0, G.ci(cx, cy + 1)),
                            s_phi.get(s0, G.ci(cx, cy)), s_phi.get(s0, G.ci(cx, cy + 1)), dph);
-              mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+              {
+                lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
+                mu_face_j<R, false>(P, C, pb, gn, gt1, gt2, dph, mL, mU, Phi);
+              }
             }
             s_fy[0][fo] = Phi[0];
             s_fy[1][fo] = Phi[1];
           }
         }
         // z face above plane k
-        if (k >= 0 && k < g.nz - 1) {
+        if (g.zface(k)) {
           R pb[NP], gn[NP];
           lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
           mu_face_diff<R, true>(P, C, pb, ownm, upm, Pzu);
           if (antitrap && mu_face_needs_j(pb)) {
             R gt1[NP], gt2[NP], dph[3];
-            lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
             const V4<R> L0 = s_phi.get(s0, G.own_c), U0 = s_phi.get(sp, G.own_c);
   #pragma unroll
             for (int a = 0; a < 3; ++a) dph[a] = (own1.v[a] - L0.v[a]) + (up1.v[a] - U0.v[a]);
-            mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+            {
+              lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
+              mu_face_j<R, true>(P, C, pb, gn, gt1, gt2, dph, ownm, upm, Pzu);
+            }
           }
         }
       }
