@@ -184,17 +184,21 @@ def run_fp32_error(steps: int) -> dict:
             "within": bool(dphi <= 2e-4 and dmu <= 1e-4)}
 
 
+STEP_SOURCES = ("pf_device.h", "pf_kernels.hip", "pf_kernels_common.h", "pf_launch.h",
+                "pf_runtime.hip", "pf_tiled.hip")
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the device sources of the sweeps; a recorded counter
-    measurement is used only while this digest is unchanged."""
+    """SHA-256 over the sources of the step's kernels and their launch
+    setup; a recorded counter measurement is used only while this digest is
+    unchanged."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1506_01684_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in STEP_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

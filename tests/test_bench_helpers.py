@@ -9,8 +9,10 @@ import bench
 
 def _fake_root(tmp_path, digest):
     root = tmp_path / "repo"
-    shutil.copytree(os.path.join(bench.ROOT, "paper_1506_01684_amd", "csrc"),
-                    root / "paper_1506_01684_amd" / "csrc")
+    csrc = root / "paper_1506_01684_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for name in bench.STEP_SOURCES:
+        shutil.copy(os.path.join(bench.ROOT, "paper_1506_01684_amd", "csrc", name), csrc / name)
     (root / "profiles").mkdir()
     rec = {"kernel_source_sha256": digest, "fetch_scale": 2.0, "write_scale": 1.0,
            "kernels": {"c2": {"mu_tiled_f64": {"fetch_kib": 100.0, "write_kib": 50.0}}}}
