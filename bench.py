@@ -203,10 +203,11 @@ def kernel_source_digest() -> str:
 
 
 def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (profiles/hbm_traffic.md), each
-    counter scaled by what it reads for a copy of known size; None when no
-    summary matches the current kernel sources."""
+    """HBM bytes per launch of `kernel` (several kernels joined by '+' are
+    summed: one sweep made of several launches) on `workload` from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary
+    (profiles/hbm_traffic.md), each counter scaled by what it reads for a copy
+    of known size; None when no summary matches the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -217,10 +218,13 @@ def recorded_traffic(kernel: str, workload: str):
     rec = json.loads(m.group(1))
     if rec.get("kernel_source_sha256") != kernel_source_digest():
         return None
-    k = rec.get("kernels", {}).get(workload, {}).get(kernel)
-    if not k:
-        return None
-    return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
+    total = 0.0
+    for name in kernel.split("+"):
+        k = rec.get("kernels", {}).get(workload, {}).get(name)
+        if not k:
+            return None
+        total += (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
+    return total
 
 
 def run_pack(count: int, steps: int, warmup: int) -> dict:
@@ -411,7 +415,9 @@ def main():
     achieved = main_run[f"{dom}_gbs"]
     real = "double" if main_run["prec"] == "fp64" else "float"
     aniso = "true" if args.workload == "c3" else "false"
-    kname = (f"mu_tiled_f{64 if real == 'double' else 32}" if dom == "mu"
+    # the FP64 mu-sweep is two launches (items with and without the
+    # anti-trapping current); the roofline covers the whole sweep
+    kname = (("mu_tiled_f64+mu_bulk_f64" if real == "double" else "mu_tiled_f32") if dom == "mu"
              else f"phi_tiled_kernel<{real}, {aniso}>")
     traffic = recorded_traffic(kname, args.workload) if args.variant == 1 else None
     line = {

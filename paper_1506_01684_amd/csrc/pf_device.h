@@ -108,6 +108,8 @@ struct DevDomain {
   double mu_fill[NM];         // mu of the liquid plane a shift adds / of the ghost plane
   void* copy[2];              // base of each 6-field copy
   void* coef;                 // PlaneCoef<R>[nz] of the running step
+  void* jfree;                // uint32 per work item of the tiled sweeps, then a count
+  int32_t nitems;             // work items of the tiled sweeps (index of that count)
   double dt, dx;
   double eps, TE, T0, G, v, zoff;
   double chi0[NP][NM], chi1[NP][NM], c0[NP][NM], c1[NP][NM];
@@ -123,6 +125,10 @@ __device__ __forceinline__ const auto& kparams(const DD& d) {
 }
 
 // ------------------------------------------------------------ math helpers
+//
+// fma_: a*b+c with one rounding.
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 //
 // FP64: hardware reciprocal / reciprocal square root refined by two Newton
 // steps (relative error about one ulp); FP32: the hardware instructions
@@ -333,15 +339,20 @@ __device__ __forceinline__ void phi_cell(const KP& P, const CP& C, const R ph[NP
 // pb: face average of phi^n; gn/gt1/gt2: normal and tangential face
 // gradient of phi^n; dph: (phi^{n+1}-phi^n)_L + (...)_U per solid phase;
 // mL/mU: mu^n at the face cells.
-// Diffusive part M_i (mu_i,U - mu_i,L)/dx of the face flux.
+// Diffusive part M_i (mu_i,U - mu_i,L)/dx of the face flux.  Here and in
+// mu_cell every rounding step is written out (fused where fma_ says so) and
+// contraction is off, so that each kernel evaluating these formulas rounds
+// them identically wherever they are inlined.
 template <typename R, bool ZF, typename KP, typename CP>
 __device__ __forceinline__ void mu_face_diff(const KP& P, const CP& C, const R pb[NP],
                                              const R mL[NM], const R mU[NM], R Phi[NM]) {
-  R M0 = R(0), M1 = R(0);
+#pragma clang fp contract(off)
+  R M0 = (R)(ZF ? C.DchiZ[0][0] : C.Dchi[0][0]) * pb[0];
+  R M1 = (R)(ZF ? C.DchiZ[0][1] : C.Dchi[0][1]) * pb[0];
 #pragma unroll
-  for (int a = 0; a < NP; ++a) {
-    M0 += (R)(ZF ? C.DchiZ[a][0] : C.Dchi[a][0]) * pb[a];
-    M1 += (R)(ZF ? C.DchiZ[a][1] : C.Dchi[a][1]) * pb[a];
+  for (int a = 1; a < NP; ++a) {
+    M0 = fma_(ZF ? C.DchiZ[a][0] : C.Dchi[a][0], pb[a], M0);
+    M1 = fma_(ZF ? C.DchiZ[a][1] : C.Dchi[a][1], pb[a], M1);
   }
   Phi[0] = M0 * (mU[0] - mL[0]) * (R)P.inv_dx;
   Phi[1] = M1 * (mU[1] - mL[1]) * (R)P.inv_dx;
@@ -404,9 +415,14 @@ __device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP]
 template <typename R, typename KP, typename CP>
 __device__ __forceinline__ void mu_cell(const KP& P, const CP& C, const R p0[NP], const R p1[NP],
                                         const R mu[NM], const R div[NM], R out[NM]) {
-  R S0 = p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2] + p0[3] * p0[3];
-  R S1 = p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2] + p1[3] * p1[3];
-  R i0 = rcp_(S0), i1 = rcp_(S1);
+#pragma clang fp contract(off)
+  R S0 = p0[0] * p0[0], S1 = p1[0] * p1[0];
+#pragma unroll
+  for (int a = 1; a < NP; ++a) {
+    S0 = fma_(p0[a], p0[a], S0);
+    S1 = fma_(p1[a], p1[a], S1);
+  }
+  const R i0 = rcp_(S0), i1 = rcp_(S1);
   R h0[NP], h1[NP];
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
@@ -419,11 +435,13 @@ __device__ __forceinline__ void mu_cell(const KP& P, const CP& C, const R p0[NP]
     R src = R(0), chi = R(0);
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-      src += (h1[a] - h0[a]) * ((R)C.chi[a][q] * mu[q] + ((R)C.cbar[a][q] - cref)) +
-             h1[a] * ((R)C.dchi[a][q] * mu[q] + (R)C.dcbar[a][q]);
-      chi += h1[a] * (R)C.chi1[a][q];
+      const R ca = fma_(C.chi[a][q], mu[q], (R)C.cbar[a][q] - cref);
+      const R ta = fma_(C.dchi[a][q], mu[q], C.dcbar[a][q]);
+      src = fma_(h1[a] - h0[a], ca, src);
+      src = fma_(h1[a], ta, src);
+      chi = fma_(h1[a], C.chi1[a][q], chi);
     }
-    out[q] = mu[q] + ((R)P.dt * div[q] - src) * rcp_(chi);
+    out[q] = fma_(fma_(P.dt, div[q], -src), rcp_(chi), mu[q]);
   }
 }
 

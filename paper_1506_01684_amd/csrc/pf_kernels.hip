@@ -44,6 +44,8 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     if (threadIdx.x == 0) d.active = 0;
     return;
   }
+  // items of this step that the phi-sweep finds free of anti-trapping faces
+  if (threadIdx.x == 0) static_cast<uint32_t*>(d.jfree)[d.nitems] = 0u;
   // Moving window: has the front passed plane window_z?  The liquid
   // fraction of that plane of the current state is summed in FP64 (strided
   // per thread, then a fixed tree); below half the plane area the step

@@ -44,54 +44,6 @@ pf_status fail(pf_status s, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-struct Layout {
-  int32_t pitch;
-  int64_t plane, fstride;  // elements
-  size_t elem;
-  size_t off_desc, off_ptrs, off_first, off_coef, off_partials, off_diag, off_map, off_fields;
-  size_t copy_bytes, total;
-};
-
-bool make_layout(const pf_domain_desc& d, Layout& L) {
-  if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return false;
-  if (d.prec != PF_FP64 && d.prec != PF_FP32) return false;
-  if (!(d.dx > 0.0) || !std::isfinite(d.dx)) return false;
-  L.elem = d.prec == PF_FP64 ? 8 : 4;
-  const int64_t row_elems = 128 / (int64_t)L.elem;
-  const int64_t pitch = (d.nx + row_elems - 1) / row_elems * row_elems;
-  if (pitch > INT32_MAX) return false;
-  L.pitch = (int32_t)pitch;
-  const long double cells = (long double)pitch * d.ny * d.nz;
-  if (cells * L.elem * 12 > (long double)(1ull << 62)) return false;
-  L.plane = pitch * (int64_t)d.ny;
-  // fields start 4 KiB apart plus a 2 KiB skew, so that equal offsets in
-  // different fields do not fall on the same memory channel; each field has
-  // nz + 1 planes, the last being the ghost plane of a Dirichlet top
-  const int64_t fe = L.plane * ((int64_t)d.nz + 1);
-  const int64_t a4k = 4096 / (int64_t)L.elem, skew = 2048 / (int64_t)L.elem;
-  L.fstride = (fe + a4k - 1) / a4k * a4k + skew;
-  size_t off = 0;
-  L.off_desc = off;
-  off = align_up(off + sizeof(DevDomain), kAlign);
-  L.off_ptrs = off;
-  off = align_up(off + sizeof(void*), kAlign);
-  L.off_first = off;
-  off = align_up(off + 2 * sizeof(int32_t), kAlign);
-  L.off_coef = off;
-  const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
-  off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
-  L.off_partials = off;
-  off = align_up(off + sizeof(double) * kDiagBlocks * kDiagValues, kAlign);
-  L.off_diag = off;
-  off = align_up(off + sizeof(double) * kDiagValues, kAlign);
-  L.off_map = off;
-  off = align_up(off + (size_t)d.nx * (size_t)d.ny, 4096);
-  L.off_fields = off;
-  L.copy_bytes = align_up((size_t)L.fstride * NFIELD * L.elem, 4096);
-  L.total = off + 2 * L.copy_bytes;
-  return true;
-}
-
 struct Tiling {
   int32_t tx, ty, zc, ntx, nty, nzc;
   int32_t xmode, rs;  // XCD y-slab order and tile rows per XCD
@@ -121,6 +73,63 @@ Tiling choose_tiling(int nx, int ny, int nz) {
   t.rs = (t.nty + 7) / 8;
   t.xmode = (8 * t.rs - t.nty) * 8 <= 8 * t.rs ? 1 : 0;
   return t;
+}
+
+struct Layout {
+  int32_t pitch;
+  int64_t plane, fstride;  // elements
+  size_t elem;
+  size_t off_desc, off_ptrs, off_first, off_coef, off_jfree, off_partials, off_diag, off_map,
+      off_fields;
+  size_t copy_bytes, total;
+};
+
+bool make_layout(const pf_domain_desc& d, Layout& L) {
+  if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return false;
+  if (d.prec != PF_FP64 && d.prec != PF_FP32) return false;
+  if (!(d.dx > 0.0) || !std::isfinite(d.dx)) return false;
+  L.elem = d.prec == PF_FP64 ? 8 : 4;
+  const int64_t row_elems = 128 / (int64_t)L.elem;
+  const int64_t pitch = (d.nx + row_elems - 1) / row_elems * row_elems;
+  if (pitch > INT32_MAX) return false;
+  L.pitch = (int32_t)pitch;
+  const long double cells = (long double)pitch * d.ny * d.nz;
+  if (cells * L.elem * 12 > (long double)(1ull << 62)) return false;
+  {  // work items of the tiled sweeps must fit the 32-bit block index
+    const int64_t tx = d.nx >= 48 ? 64 : 32, ty = kTileThreads / tx;
+    const int64_t items = ((d.nx + tx - 1) / tx) * ((d.ny + ty - 1) / ty) * (int64_t)d.nz;
+    if (items > (int64_t)1 << 28) return false;
+  }
+  L.plane = pitch * (int64_t)d.ny;
+  // fields start 4 KiB apart plus a 2 KiB skew, so that equal offsets in
+  // different fields do not fall on the same memory channel; each field has
+  // nz + 1 planes, the last being the ghost plane of a Dirichlet top
+  const int64_t fe = L.plane * ((int64_t)d.nz + 1);
+  const int64_t a4k = 4096 / (int64_t)L.elem, skew = 2048 / (int64_t)L.elem;
+  L.fstride = (fe + a4k - 1) / a4k * a4k + skew;
+  size_t off = 0;
+  L.off_desc = off;
+  off = align_up(off + sizeof(DevDomain), kAlign);
+  L.off_ptrs = off;
+  off = align_up(off + sizeof(void*), kAlign);
+  L.off_first = off;
+  off = align_up(off + 2 * sizeof(int32_t), kAlign);
+  L.off_coef = off;
+  const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
+  off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
+  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and a count
+  off = align_up(off + sizeof(uint32_t) * ((size_t)choose_tiling(d.nx, d.ny, d.nz).blocks() + 1),
+                 kAlign);
+  L.off_partials = off;
+  off = align_up(off + sizeof(double) * kDiagBlocks * kDiagValues, kAlign);
+  L.off_diag = off;
+  off = align_up(off + sizeof(double) * kDiagValues, kAlign);
+  L.off_map = off;
+  off = align_up(off + (size_t)d.nx * (size_t)d.ny, 4096);
+  L.off_fields = off;
+  L.copy_bytes = align_up((size_t)L.fstride * NFIELD * L.elem, 4096);
+  L.total = off + 2 * L.copy_bytes;
+  return true;
 }
 
 uint64_t splitmix64_next(uint64_t& s) {
@@ -408,6 +417,8 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
   h.copy[0] = d->fields(0);
   h.copy[1] = d->fields(1);
   h.coef = d->base + L.off_coef;
+  h.jfree = d->base + L.off_jfree;
+  h.nitems = d->T.blocks();
   h.dx = desc->dx;
   int32_t first[2] = {0, d->T.blocks()};
   DevDomain* self = d->dev;

@@ -16,6 +16,10 @@
 //     wherever it is computed;
 //   - the next plane's loads are issued before the face stage and written
 //     to LDS after it, so their latency overlaps the arithmetic.
+// The FP64 mu-sweep runs as two kernels over the same items: items whose
+// faces cannot carry the anti-trapping current (no liquid, or only liquid,
+// around them; classified by the phi-sweep) go to a lighter kernel that
+// stages one phi^n plane and no phi^{n+1} neighbours.
 // LDS layout avoids bank conflicts: phi is stored as 16-byte vectors
 // (two doubles or four floats per lane access) and face values as
 // structure of arrays (consecutive lanes touch consecutive words).
@@ -252,16 +256,47 @@ struct ItemCtx {
   Geo g;
   const PF_CONST PlaneCoef<R>* tab;
   Copy src, dst;
+  uint32_t* jf;  // the item's classification word (written by the phi-sweep)
+  uint32_t* jn;  // the step's count of light items
 };
 
+// Item classification for the mu-sweep.  The anti-trapping current of a
+// face vanishes unless a solid phase and the liquid are both present on it
+// (Eq. 4 weights each solid by its product with the liquid), so it vanishes
+// on every face of an item when all phi^n cells those faces touch hold no
+// liquid, or all hold pure liquid.  The FP64 phi-sweep, which loads all of
+// these cells (the tile, its halo ring and the planes z0-1 .. z1), records this
+// per wave: byte w of the word has bit 0 set when wave w saw no liquid and
+// bit 1 when it saw only liquid.  Bits are set only with the shortcuts on
+// and mu not frozen; without the anti-trapping term every item qualifies.
+// The phi-sweep also counts the qualifying items of the step; the split
+// into two kernels is used only when they are at least kBulkMinPct percent
+// of all items: each kernel's last round of items runs on a partly idle
+// chip, which a small share of light items does not repay.
+constexpr uint64_t kBulkMinPct = 60;
+__device__ __forceinline__ bool item_jfree(uint32_t f) {
+  return ((f & (f >> 8) & (f >> 16) & (f >> 24)) & 3u) != 0;
+}
+
+// jsel < 0: every item; 0: items that need the anti-trapping current;
+// 1: items that do not.
 template <typename R>
 __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t* first,
-                                           int ndom, int item, int t, ItemCtx<R>& X) {
+                                           int ndom, int item, int t, ItemCtx<R>& X,
+                                           int jsel = -1) {
   const int di = find_domain(first, ndom, item);
   const PF_CONST DevDomain& d = domain_at(doms, di);
   if (!d.active) return false;  // uniform over the work group
+  const int local = item - first_item(first, di);
+  X.jf = static_cast<uint32_t*>(d.jfree) + local;
+  X.jn = static_cast<uint32_t*>(d.jfree) + d.nitems;
+  if (jsel >= 0) {  // uniform over the work group
+    bool light = item_jfree(*to_const(X.jf));
+    if (light) light = (uint64_t)*to_const(X.jn) * 100 >= (uint64_t)d.nitems * kBulkMinPct;
+    if (light != (jsel == 1)) return false;
+  }
   X.dp = &d;
-  X.G = make_tile<R>(d, item - first_item(first, di), t);
+  X.G = make_tile<R>(d, local, t);
   if (!X.G.item_ok) return false;  // padding block (uniform)
   X.g = make_geo(d);
   X.tab = to_const(static_cast<const PlaneCoef<R>*>(d.coef));
@@ -282,6 +317,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
   __shared__ LdsPhi<R, NSLOT> s_phi;
   __shared__ R s_fx[2 * NP][kMaxFx];  // F[0..3], S[0..3] of x faces
   __shared__ R s_fy[2 * NP][kMaxFy];
+  __shared__ uint8_t s_jw[4];          // per-wave bytes of the item's classification word
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
 
@@ -297,11 +333,28 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
     const bool shortcut = P.shortcuts != 0;
     const int kstart = G.z0 - 1;
 
+    // liquid content of every phi^n cell this item loads (item_jfree; the
+    // FP64 mu-sweep only)
+    constexpr bool CLASSIFY = sizeof(R) == 8;
+    bool no_liq = true, only_liq = true;
+    const auto note = [&](const V4<R>& v) {
+      if constexpr (CLASSIFY) {
+        no_liq = no_liq && v.v[LQ] == R(0);
+        only_liq = only_liq && v.v[0] == R(0) && v.v[1] == R(0) && v.v[2] == R(0);
+      }
+    };
+
     // prime the LDS ring with planes kstart-1 .. kstart+1 (ANISO) or kstart
     for (int p = kstart - (NSLOT == 3 ? 1 : 0); p <= kstart + (NSLOT == 3 ? 1 : 0); ++p) {
       const int pc = g.zc(p), sl = slot_of(NSLOT, p);
-      s_phi.put(sl, G.own_c, load4<R>(src, pc, G.own_b));
-      if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, load4<R>(src, pc, G.halo_b));
+      const V4<R> vo = load4<R>(src, pc, G.own_b);
+      note(vo);
+      s_phi.put(sl, G.own_c, vo);
+      if (G.halo_c >= 0) {
+        const V4<R> vh = load4<R>(src, pc, G.halo_b);
+        note(vh);
+        s_phi.put(sl, G.halo_c, vh);
+      }
     }
     V4<R> own_k = load4<R>(src, g.zc(kstart), G.own_b);
     __syncthreads();
@@ -393,7 +446,11 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       {
         const int sl = slot_of(NSLOT, k + AHEAD);
         s_phi.put(sl, G.own_c, nxt_own);
-        if (G.halo_c >= 0) s_phi.put(sl, G.halo_c, nxt_halo);
+        note(nxt_own);
+        if (G.halo_c >= 0) {
+          s_phi.put(sl, G.halo_c, nxt_halo);
+          note(nxt_halo);
+        }
       }
       if (cells && G.valid) {
         const int fl = G.ly * (G.tx + 1) + G.lx;  // lower x face; upper is fl+1
@@ -428,6 +485,19 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       if constexpr (!ANISO) own_k = nxt_own;
       __syncthreads();  // B2: LDS plane and faces consumed
     }
+    if constexpr (CLASSIFY) {
+      uint32_t b = 0;
+      if (shortcut && !P.mu_frozen)
+        b = !P.antitrap ? 3u : (__all(no_liq) ? 1u : 0u) | (__all(only_liq) ? 2u : 0u);
+      if (lane == 0) s_jw[wave] = (uint8_t)b;
+      __syncthreads();
+      if (t == 0) {
+        const uint32_t w = (uint32_t)s_jw[0] | (uint32_t)s_jw[1] << 8 | (uint32_t)s_jw[2] << 16 |
+                           (uint32_t)s_jw[3] << 24;
+        *to_global(X.jf) = w;
+        if (item_jfree(w)) atomicAdd(X.jn, 1u);
+      }
+    }
   }
 }
 
@@ -456,7 +526,9 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     ItemCtx<R> X;
-    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    // FP64: the items that need the anti-trapping current (mu_bulk_f64
+    // takes the rest); FP32: every item
+    if (!item_setup(doms, first, ndom, item, t, X, sizeof(R) == 8 ? 0 : -1)) continue;
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const auto& P = kparams<R>(*X.dp);
@@ -743,6 +815,146 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4)
   mu_tiled_body<float>(doms, first, ndom, total);
 }
 
+// mu-sweep of the items whose faces carry no anti-trapping current
+// (item_jfree): only the diffusive fluxes M grad mu, which need phi^n at
+// the face cells (one LDS plane and the own column in registers, as in the
+// isotropic phi-sweep) and mu^n; no tangential gradients and no phi^{n+1}
+// neighbours.  Every face value and the cell stage are the same operations
+// on the same operands as in mu_tiled_body, so both kernels give bitwise
+// the same mu^{n+1} on such an item.
+template <typename R>
+__device__ __forceinline__ void mu_bulk_body(DevDomain* const* doms, const int32_t* first, int ndom,
+                                             int total) {
+  __shared__ LdsPhi<R, 1> s_phi;  // phi^n of plane k
+  __shared__ LdsMu<R> s_mu;       // mu^n of plane k
+  __shared__ R s_fx[NM][kMaxFx];
+  __shared__ R s_fy[NM][kMaxFy];
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    ItemCtx<R> X;
+    if (!item_setup(doms, first, ndom, item, t, X, 1)) continue;
+    const TileGeo& G = X.G;
+    const Geo& g = X.g;
+    const auto& P = kparams<R>(*X.dp);
+    const Copy& src = X.src;  // phi^n (fields 0-3), mu^n (4-5)
+    const Copy& dst = X.dst;  // phi^{n+1}, mu^{n+1}
+    const R inv_dx = (R)P.inv_dx;
+    const bool ex_ok = lane < G.ty && G.y0 + lane < g.ny;
+    const bool ey_ok = lane < G.tx && G.x0 + lane < g.nx;
+    const int kstart = G.z0 - 1;
+
+    const int kc0 = g.zc(kstart);
+    V4<R> own_k = load4<R>(src, kc0, G.own_b);
+    R ownm[NM] = {ldg<R>(src.at(4, kc0), G.own_b), ldg<R>(src.at(5, kc0), G.own_b)};
+    s_phi.put(0, G.own_c, own_k);
+    s_mu.put(G.own_c, ownm);
+    if (G.halo_c >= 0) {
+      s_phi.put(0, G.halo_c, load4<R>(src, kc0, G.halo_b));
+      const R hm[NM] = {ldg<R>(src.at(4, kc0), G.halo_b), ldg<R>(src.at(5, kc0), G.halo_b)};
+      s_mu.put(G.halo_c, hm);
+    }
+    __syncthreads();
+
+    R Pzl[NM] = {R(0), R(0)};
+    for (int k = kstart; k < G.z1; ++k) {
+      const bool cells = k >= G.z0;
+      // plane k+1 (phi^n, mu^n: own column and halo cell), then phi^{n+1}
+      // of the own cell at plane k (cell stage only)
+      const int k1 = g.zp(k);
+      const V4<R> nxt_own = load4<R>(src, k1, G.own_b);
+      const R upm[NM] = {ldg<R>(src.at(4, k1), G.own_b), ldg<R>(src.at(5, k1), G.own_b)};
+      V4<R> nxt_halo;
+      R nxt_hm[NM] = {R(0), R(0)};
+      if (G.halo_c >= 0) {
+        nxt_halo = load4<R>(src, k1, G.halo_b);
+        nxt_hm[0] = ldg<R>(src.at(4, k1), G.halo_b);
+        nxt_hm[1] = ldg<R>(src.at(5, k1), G.halo_b);
+      }
+      V4<R> own1;
+      if (cells && G.valid) own1 = load4<R>(dst, k, G.own_b);
+      const int kk = k < 0 ? 0 : k;
+      const auto& C = X.tab[kk];
+      if (cells) {
+        const bool ex = ex_ok && wave == ((k + 1) & 3);
+        const bool ey = ey_ok && wave == (k & 3);
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          const bool edge = r == 1;
+          if (edge ? !ex : !G.valid) continue;
+          const int cx = edge ? 0 : G.lx + 1, cy = edge ? lane + 1 : G.ly + 1;
+          const int fo = edge ? lane * (G.tx + 1) : G.ly * (G.tx + 1) + G.lx + 1;
+          R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
+          lds_face_normal<R, 0>(s_phi, G, cx, cy, 0, 0, inv_dx, pb, gn);
+          s_mu.get(G.ci(cx, cy), mL);
+          s_mu.get(G.ci(cx + 1, cy), mU);
+          mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+          s_fx[0][fo] = Phi[0];
+          s_fx[1][fo] = Phi[1];
+        }
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          const bool edge = r == 1;
+          if (edge ? !ey : !G.valid) continue;
+          const int cx = edge ? lane + 1 : G.lx + 1, cy = edge ? 0 : G.ly + 1;
+          const int fo = edge ? lane : (G.ly + 1) * G.tx + G.lx;
+          R pb[NP], gn[NP], mL[NM], mU[NM], Phi[NM];
+          lds_face_normal<R, 1>(s_phi, G, cx, cy, 0, 0, inv_dx, pb, gn);
+          s_mu.get(G.ci(cx, cy), mL);
+          s_mu.get(G.ci(cx, cy + 1), mU);
+          mu_face_diff<R, false>(P, C, pb, mL, mU, Phi);
+          s_fy[0][fo] = Phi[0];
+          s_fy[1][fo] = Phi[1];
+        }
+      }
+      // z face above plane k: own column at k and k+1
+      R Pzu[NM] = {R(0), R(0)};
+      if (g.zface(k)) {
+        R pb[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) pb[a] = R(0.5) * (own_k.v[a] + nxt_own.v[a]);
+        mu_face_diff<R, true>(P, C, pb, ownm, upm, Pzu);
+      }
+      __syncthreads();  // B1: faces visible; phi and mu planes of k free
+      s_phi.put(0, G.own_c, nxt_own);
+      s_mu.put(G.own_c, upm);
+      if (G.halo_c >= 0) {
+        s_phi.put(0, G.halo_c, nxt_halo);
+        s_mu.put(G.halo_c, nxt_hm);
+      }
+      if (cells && G.valid) {
+        const int fl = G.ly * (G.tx + 1) + G.lx;
+        const int yl = G.ly * G.tx + G.lx;
+        R div[NM], out[NM];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+          div[q] = R(0);
+          div[q] += s_fx[q][fl + 1] - s_fx[q][fl];
+          div[q] += s_fy[q][yl + G.tx] - s_fy[q][yl];
+          div[q] = (div[q] + (Pzu[q] - Pzl[q])) * inv_dx;
+        }
+        mu_cell<R>(P, C, own_k.v, own1.v, ownm, div, out);
+        stg<R>(dst.at(4, k), G.own_b, out[0]);
+        stg<R>(dst.at(5, k), G.own_b, out[1]);
+      }
+      Pzl[0] = Pzu[0];
+      Pzl[1] = Pzu[1];
+      own_k = nxt_own;
+      ownm[0] = upm[0];
+      ownm[1] = upm[1];
+      __syncthreads();  // B2: LDS planes and faces consumed
+    }
+  }
+}
+
+// FP64 only: in FP32 the tiled kernel, at four waves per SIMD, is already
+// held to 128 VGPRs and evaluates these items about as fast on its own.
+__global__ __launch_bounds__(kTileThreads) void mu_bulk_f64(DevDomain* const* doms, const int32_t* first,
+                                                            int ndom, int total) {
+  mu_bulk_body<double>(doms, first, ndom, total);
+}
+
 // --------------------------------------------------------------- launches
 
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
@@ -761,12 +973,18 @@ hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_
   return hipGetLastError();
 }
 
+// The FP64 mu-sweep is two launches over the same items: mu_tiled_f64
+// takes the items whose faces may carry the anti-trapping current,
+// mu_bulk_f64 the rest (all items go to mu_tiled_f64 in a step with few
+// light ones).  The FP32 sweep is one launch.
 hipError_t launch_mu_tiled(const LaunchSet& L, int prec, hipStream_t s) {
   const int grid = L.total;
-  if (prec == 0)
+  if (prec == 0) {
     mu_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
-  else
+    mu_bulk_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  } else {
     mu_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  }
   return hipGetLastError();
 }
 
