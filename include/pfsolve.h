@@ -140,6 +140,13 @@ typedef struct {
   double phi_min, phi_max;
   int64_t nonfinite;      /* cells holding a NaN or Inf in any field      */
   int64_t window_shifts;  /* moving-window shifts since pf_init_fields    */
+  int32_t light_items;    /* work items of the last step whose faces cannot
+                           * carry the anti-trapping current (Eq. 4: no
+                           * liquid, or only liquid, around them), counted
+                           * by the FP64 tiled sweep; 0 in FP32, with the
+                           * direct variant, with the shortcuts off, and
+                           * before the first step                         */
+  int32_t work_items;     /* work items per sweep of this domain           */
 } pf_diag;
 
 /* Device bytes a domain needs (both field copies, each with one extra

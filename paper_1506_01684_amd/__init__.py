@@ -234,6 +234,7 @@ class Domain:
             "max_simplex_dev": dg.max_simplex_dev, "phi_min": dg.phi_min,
             "phi_max": dg.phi_max, "nonfinite": dg.nonfinite,
             "window_shifts": dg.window_shifts,
+            "light_items": dg.light_items, "work_items": dg.work_items,
         }
 
 

@@ -60,6 +60,8 @@ class PfDiag(C.Structure):
         ("t", _D), ("step", C.c_int64), ("sum_c", _D * 2), ("sum_phi", _D * 4),
         ("max_simplex_dev", _D), ("phi_min", _D), ("phi_max", _D), ("nonfinite", C.c_int64),
         ("window_shifts", C.c_int64),
+        ("light_items", C.c_int32),
+        ("work_items", C.c_int32),
     ]
 
 

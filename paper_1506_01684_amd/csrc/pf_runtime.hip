@@ -527,6 +527,9 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   h.shift_now = 0;
   h.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
+  // no step has classified the items yet
+  PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
+                        sizeof(uint32_t), d->stream));
   if (in->kind == PF_INIT_VORONOI) {
     if (in->nseeds < 0 || in->solid_height < 0)
       return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
@@ -698,6 +701,11 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->phi_max = v[8];
     diag->nonfinite = (int64_t)v[9];
     diag->window_shifts = cur.shifts;
+    uint32_t light = 0;
+    PF_HIP(hipMemcpy(&light, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(),
+                     sizeof(light), hipMemcpyDeviceToHost));
+    diag->light_items = (int32_t)light;
+    diag->work_items = d->T.blocks();
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
   }

@@ -1,0 +1,62 @@
+"""GPU tests of the FP64 mu-sweep split by work-item class: an item whose
+faces cannot carry the anti-trapping current (Eq. 4 weights each solid by
+its product with the liquid, so no liquid, or only liquid, around the item
+means none) is evaluated by a lighter kernel when such items are the large
+majority of a step; the result is bitwise the one of the full kernel."""
+import numpy as np
+import pytest
+
+import oracle
+import pfinputs
+from tests.gpu_util import gpu_domain, lib, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(shape, p, prec, steps, shortcuts, voronoi, variant=1):
+    q = dict(p)
+    q["shortcuts"] = shortcuts
+    d = gpu_domain(shape, q, prec, variant, voronoi=voronoi)
+    d.step(steps)
+    out = d.read()
+    dg = d.diagnostics()
+    d.close()
+    return out, dg
+
+
+@pytest.mark.parametrize("hs,aniso", [(4, False), (4, True), (40, False)])
+def test_split_is_bitwise_exact(hs, aniso):
+    """Mostly liquid (hs = 4): most items are light and the split runs;
+    mostly solid (hs = 40 of 64): liquid films along the lamella boundaries
+    make most items heavy.  Either way shortcuts on equals shortcuts off."""
+    shape = (64, 40, 70)
+    p = pfinputs.p0_params(solid_height=hs, delta_sl=0.05 if aniso else 0.0)
+    p["dt"] = oracle.default_dt(p, shape)
+    a, da = _run(shape, p, "fp64", 12, 1, (5, 9, hs))
+    b, db = _run(shape, p, "fp64", 12, 0, (5, 9, hs))
+    frac = da["light_items"] / da["work_items"]
+    log(f"split hs={hs} aniso={aniso}: light items {da['light_items']} of {da['work_items']} "
+        f"({frac:.2f}), max |dmu| {np.max(np.abs(a[1] - b[1])):.1e}")
+    assert db["light_items"] == 0
+    if hs == 4:
+        assert frac >= 0.6  # the light kernel really ran
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_light_items_reported_only_for_the_fp64_tiled_sweep():
+    pf = lib()
+    shape = (32, 24, 40)
+    p = pfinputs.p0_params(solid_height=3)
+    p["dt"] = oracle.default_dt(p, shape)
+    d = gpu_domain(shape, p, "fp64", 1, voronoi=(3, 4, 3))
+    assert d.diagnostics()["light_items"] == 0  # no step yet
+    d.step(2)
+    dg = d.diagnostics()
+    assert 0 < dg["light_items"] <= dg["work_items"]
+    d.close()
+    try:
+        for prec, var in (("fp32", 1), ("fp64", 0)):
+            _, dg = _run(shape, p, prec, 2, 1, (3, 4, 3), variant=var)
+            assert dg["light_items"] == 0, (prec, var)
+    finally:
+        pf.set_variant(1)
