@@ -74,6 +74,8 @@ def lib():
                                    C.POINTER(C.c_int64), _PD, _PD, i]),
             "orc_init_voronoi": (None, [G, C.c_uint64, C.c_int32, C.c_int32, _PD, _PD, _PD]),
             "orc_diagnostics": (None, [G, P, _D, _PD, _PD, C.POINTER(OrcDiag)]),
+            "orc_mesh_phase": (C.c_int64, [G, _PD, C.c_int32, _D, C.POINTER(C.c_float),
+                                          C.c_int64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -257,6 +259,20 @@ def run_window(p, phi, mu, nsteps, zw, mu_fill=(0.0, 0.0), step0=0, shifts=0, nt
     if rc != 0:
         raise MemoryError("oracle run: allocation failed")
     return phi, mu, sh.value
+
+
+def mesh_phase(phi, phase: int, iso: float = 0.5) -> np.ndarray:
+    """Marching-cubes mesh of phi[phase] = iso (output path, Sec. 3.2; rules
+    in pf_oracle_mesh.c): float32 array [ntri, 3, 3] of triangle vertices in
+    cell-index units, in cube order, normals out of the phase.  phi may be
+    [4, nz, ny, nx] (or any [k, nz, ny, nx] with phase < k)."""
+    phi = _f64(phi)
+    g = make_grid(_shape_of(phi))
+    n = lib().orc_mesh_phase(C.byref(g), _ptr(phi), int(phase), float(iso), None, 0)
+    out = np.empty((max(n, 1), 3, 3), np.float32)
+    lib().orc_mesh_phase(C.byref(g), _ptr(phi), int(phase), float(iso),
+                         out.ctypes.data_as(C.POINTER(C.c_float)), int(n))
+    return out[:n]
 
 
 def init_voronoi(shape, seed, nseeds, solid_height, mu_init=(0.0, 0.0), dx=1.0):

@@ -150,6 +150,14 @@ void orc_init_voronoi(const orc_grid* g, uint64_t seed, int32_t nseeds,
 void orc_diagnostics(const orc_grid* g, const orc_params* p, double t,
                      const double* phi, const double* mu, orc_diag* out);
 
+/* Interface mesh of phase `phase` (output path, Sec. 3.2): marching cubes
+ * over the cell-centre grid for phi_phase = iso, reading and rules at the
+ * top of pf_oracle_mesh.c.  Writes up to `capacity` triangles (9 floats
+ * each: three vertices xyz, cell-index units) in cube order (x fastest,
+ * then y, z) and returns the total count. */
+int64_t orc_mesh_phase(const orc_grid* g, const double* phi, int32_t phase, double iso,
+                       float* out, int64_t capacity);
+
 #ifdef __cplusplus
 }
 #endif
