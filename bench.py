@@ -128,6 +128,59 @@ def run_window(steps: int, variant: int) -> dict:
                                   "shifts": sh["window_shifts"]}}
 
 
+def run_output(steps: int = 20, reps: int = 5) -> dict:
+    """Output path on the headline domain after `steps` steps: the
+    marching-cubes mesh of each phase (extraction into a device buffer,
+    counted and synchronised, per call) and one FP32 checkpoint save/load
+    through a file in /tmp."""
+    import ctypes as C
+    import tempfile
+
+    import torch
+
+    import paper_1506_01684_amd as pf
+    from paper_1506_01684_amd import _capi as A
+    import pfinputs
+
+    w = pfinputs.workload("c2")
+    nz, ny, nx = w["shape"]
+    pf.set_variant(1)
+    d = pf.Domain(w["shape"], "fp64")
+    d.set_params(w["params"])
+    d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
+    d.step(steps)
+    d.sync()
+    lib = pf.load()
+    out = {"steps": steps, "phases": []}
+    n = C.c_int64()
+    for phase in range(4):
+        empty = A.PfDeviceBuffer(None, 0)
+        lib.pf_mesh_phase(d.handle, phase, 0.5, C.byref(empty), C.byref(n))
+        buf = torch.empty(max(n.value, 1) * 9, dtype=torch.float32, device="cuda")
+        dev = A.PfDeviceBuffer(C.c_void_p(buf.data_ptr()), n.value * 36)
+        lib.pf_mesh_phase(d.handle, phase, 0.5, C.byref(dev), C.byref(n))  # warm-up
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = lib.pf_mesh_phase(d.handle, phase, 0.5, C.byref(dev), C.byref(n))
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        if st != A.PF_OK:
+            raise RuntimeError(f"mesh phase {phase}: status {st}")
+        out["phases"].append({"phase": phase, "triangles": n.value, "ms": round(ms, 3),
+                              "phi_read_gbs": round(8.0 * nx * ny * nz / (ms * 1e-3) / 1e9, 1)})
+        del buf
+    with tempfile.TemporaryDirectory(dir="/tmp") as tmp:
+        path = os.path.join(tmp, "c2.pfc")
+        t0 = time.perf_counter()
+        d.save_checkpoint(path)
+        t1 = time.perf_counter()
+        d.load_checkpoint(path)
+        t2 = time.perf_counter()
+        out["checkpoint"] = {"bytes": os.path.getsize(path), "save_s": round(t1 - t0, 3),
+                             "load_s": round(t2 - t1, 3)}
+    d.close()
+    return out
+
+
 def run_stream(nbytes: int = 2 << 30, reps: int = 10) -> dict:
     """STREAM-style device bandwidth with torch kernels on FP32 arrays of
     nbytes each: copy (b = a, 2 nbytes per pass) and add (b = a + c,
@@ -377,6 +430,8 @@ def main():
                     help="skip the moving-window timings of the headline domain")
     ap.add_argument("--no-scenarios", action="store_true",
                     help="skip the interface/solid/liquid timings of the headline domain")
+    ap.add_argument("--no-output", action="store_true",
+                    help="skip the mesh and checkpoint timings of the headline domain")
     ap.add_argument("--pack-steps", type=int, default=100)
     ap.add_argument("--serve-count", type=int, default=64)
     ap.add_argument("--full-serving", action="store_true",
@@ -467,6 +522,9 @@ def main():
     if not args.no_window and args.workload == "c2":
         _log("[bench] moving window")
         line["window"] = run_window(args.steps // 2, args.variant)
+    if not args.no_output and args.workload == "c2":
+        _log("[bench] output path: meshes and checkpoint")
+        line["output"] = run_output()
     if not args.no_fp32 and args.workload == "c2":
         r32 = run_gpu("c3", args.fp32_steps, 5, args.variant, args.shortcuts)
         line["fp32"] = {

@@ -46,7 +46,8 @@ typedef enum {
   PF_ERR_UNSTABLE = 3,    /* explicit dt above the stability bound        */
   PF_ERR_OOM = 4,         /* device allocation failed / buffer too small  */
   PF_ERR_DEVICE = 5,      /* a HIP runtime call failed                    */
-  PF_ERR_NONFINITE = 6    /* diagnostics found NaN or Inf in the fields   */
+  PF_ERR_NONFINITE = 6,   /* diagnostics found NaN or Inf in the fields   */
+  PF_ERR_IO = 7           /* a file could not be opened, read or written  */
 } pf_status;
 
 /* Storage and arithmetic precision of a domain.  PF_FP32 stores fields and
@@ -211,6 +212,48 @@ pf_status pf_get_step(const pf_domain* d, int64_t* step);
 
 /* Synchronise and free owned memory.  NULL is accepted. */
 void pf_destroy(pf_domain* d);
+
+/* ------------------------------------------------------------ output path
+ * Sec. 3.2 (Input/Output): the arithmetic is FP64, checkpoints hold the
+ * state in single precision, and results are written as triangle meshes of
+ * the interfaces, one per phase, from a marching-cubes pass over phi.  None
+ * of these calls is part of the time step.
+ *
+ * Checkpoint file, little endian: a 64-byte header
+ *   char magic[8] = "PFCKPT01"; int32 nx, ny, nz; int32 prec (of the domain
+ *   that wrote it); int64 step; int64 window_shifts; double dx; double dt;
+ *   8 zero bytes
+ * followed by phi_0..phi_3, mu_0, mu_1 as float32, each [z][y][x]
+ * unpadded (24 bytes per cell).  FP64 values are rounded to nearest. */
+
+/* Write the current state of `d` (after pf_init_fields) to the file `path`,
+ * replacing it.  Synchronises.  The domain's second field copy serves as
+ * staging space; the state and the step are unchanged.  INVALID_ARG for a
+ * NULL argument, STATE before pf_init_fields, IO if the file cannot be
+ * written. */
+pf_status pf_checkpoint_save(pf_domain* d, const char* path);
+
+/* Replace the state of `d` (after pf_set_params) with the checkpoint in
+ * `path`, written for the same nx, ny, nz by a domain of either precision:
+ * fields widened from float, step and window shifts from the header, so
+ * t = step dt with this domain's dt.  Synchronises.  INVALID_ARG for a NULL
+ * argument, a header that is not a checkpoint or a size mismatch, STATE
+ * before pf_set_params, IO if the file cannot be read in full. */
+pf_status pf_checkpoint_load(pf_domain* d, const char* path);
+
+/* Triangle mesh of the interface of phase `phase` (0..3): the surface
+ * phi_phase = iso, iso finite, over the cubes of eight neighbouring cell
+ * centres, periodic in x and y, open at the first and last z planes.
+ * Vertices are in cell-index units (cell (x,y,z) at (x,y,z)); a cube past
+ * the last column or row reaches the periodic image at x = nx or y = ny.
+ * Each triangle is 9 floats (three vertices x, y, z), wound so that its
+ * normal points out of the phase (towards phi_phase < iso).  `out` is a
+ * caller-owned device buffer (base may be NULL when bytes is 0); up to
+ * bytes / 36 triangles are written, in no fixed order.  *ntri receives the
+ * total.  Returns INVALID_ARG (after filling *ntri and the buffer) when the
+ * total exceeds the buffer, STATE before pf_init_fields.  Synchronises. */
+pf_status pf_mesh_phase(pf_domain* d, int32_t phase, double iso, const pf_device_buffer* out,
+                        int64_t* ntri);
 
 /* Batched stepping (many independent domains of one precision).  Each pack
  * step runs the per-plane coefficient kernel, the phi-sweep and the

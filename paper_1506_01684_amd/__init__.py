@@ -224,6 +224,32 @@ class Domain:
                                      mu.ctypes.data_as(C.POINTER(C.c_double)), None))
         return phi, mu
 
+    # ------------------------------------------------------------ output
+    def save_checkpoint(self, path: str):
+        """FP32 checkpoint of the current state (format in include/pfsolve.h)."""
+        _check(load().pf_checkpoint_save(self.handle, os.fsencode(path)))
+
+    def load_checkpoint(self, path: str):
+        """Replace the state with a checkpoint of the same nx, ny, nz."""
+        _check(load().pf_checkpoint_load(self.handle, os.fsencode(path)))
+
+    def mesh(self, phase: int, iso: float = 0.5):
+        """Interface mesh of one phase on the GPU: float32 array [ntri, 3, 3]
+        of triangle vertices (cell-index units), in no fixed order.  Counts
+        first, then extracts into a device buffer of the exact size."""
+        import torch
+
+        lib = load()
+        n = C.c_int64()
+        empty = A.PfDeviceBuffer(None, 0)
+        st = lib.pf_mesh_phase(self.handle, int(phase), float(iso), C.byref(empty), C.byref(n))
+        if st not in (A.PF_OK, A.PF_ERR_INVALID_ARG) or (st != A.PF_OK and n.value == 0):
+            _check(st)
+        buf = torch.empty(max(n.value, 1) * 9, dtype=torch.float32, device="cuda")
+        dev = A.PfDeviceBuffer(C.c_void_p(buf.data_ptr()), n.value * 36)
+        _check(lib.pf_mesh_phase(self.handle, int(phase), float(iso), C.byref(dev), C.byref(n)))
+        return buf[: n.value * 9].cpu().numpy().reshape(-1, 3, 3)
+
     def diagnostics(self, raise_nonfinite: bool = True) -> dict:
         dg = A.PfDiag()
         st = load().pf_read_fields(self.handle, None, None, C.byref(dg))

@@ -10,9 +10,10 @@ LIB_PATH = os.path.join(HERE, "libpfsolve.so")
 _D = C.c_double
 
 PF_OK, PF_ERR_INVALID_ARG, PF_ERR_STATE, PF_ERR_UNSTABLE = 0, 1, 2, 3
-PF_ERR_OOM, PF_ERR_DEVICE, PF_ERR_NONFINITE = 4, 5, 6
+PF_ERR_OOM, PF_ERR_DEVICE, PF_ERR_NONFINITE, PF_ERR_IO = 4, 5, 6, 7
 STATUS_NAMES = {
     0: "OK", 1: "INVALID_ARG", 2: "STATE", 3: "UNSTABLE", 4: "OOM", 5: "DEVICE", 6: "NONFINITE",
+    7: "IO",
 }
 PF_FP64, PF_FP32 = 0, 1
 PF_INIT_VORONOI, PF_INIT_HOST = 0, 1
@@ -23,6 +24,7 @@ EXPORTS = [
     "pf_set_time", "pf_step", "pf_step_timed", "pf_sync", "pf_read_fields", "pf_get_step",
     "pf_destroy", "pf_pack_create", "pf_pack_add", "pf_pack_step", "pf_pack_remaining",
     "pf_pack_remove", "pf_pack_sync", "pf_pack_destroy", "pf_set_variant", "pf_last_error",
+    "pf_checkpoint_save", "pf_checkpoint_load", "pf_mesh_phase",
 ]
 
 
@@ -91,6 +93,9 @@ def declare(lib: C.CDLL) -> C.CDLL:
         "pf_pack_destroy": (None, [P]),
         "pf_set_variant": (C.c_int, [I32]),
         "pf_last_error": (C.c_char_p, []),
+        "pf_checkpoint_save": (C.c_int, [P, C.c_char_p]),
+        "pf_checkpoint_load": (C.c_int, [P, C.c_char_p]),
+        "pf_mesh_phase": (C.c_int, [P, I32, _D, C.POINTER(PfDeviceBuffer), C.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfsolve.so")
-SOURCES = ["pf_runtime.hip", "pf_kernels.hip", "pf_tiled.hip"]
+SOURCES = ["pf_runtime.hip", "pf_kernels.hip", "pf_tiled.hip", "pf_io.hip"]
 HEADERS = ["pf_device.h", "pf_launch.h", "pf_kernels_common.h"]
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <atomic>
 #include <cmath>
 #include <cstddef>
@@ -79,8 +80,8 @@ struct Layout {
   int32_t pitch;
   int64_t plane, fstride;  // elements
   size_t elem;
-  size_t off_desc, off_ptrs, off_first, off_coef, off_jfree, off_partials, off_diag, off_map,
-      off_fields;
+  size_t off_desc, off_ptrs, off_first, off_coef, off_jfree, off_mesh, off_partials, off_diag,
+      off_map, off_fields;
   size_t copy_bytes, total;
 };
 
@@ -120,6 +121,8 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and a count
   off = align_up(off + sizeof(uint32_t) * ((size_t)choose_tiling(d.nx, d.ny, d.nz).blocks() + 1),
                  kAlign);
+  L.off_mesh = off;  // triangle counter of pf_mesh_phase
+  off = align_up(off + sizeof(unsigned long long), kAlign);
   L.off_partials = off;
   off = align_up(off + sizeof(double) * kDiagBlocks * kDiagValues, kAlign);
   L.off_diag = off;
@@ -721,6 +724,151 @@ void pf_destroy(pf_domain* d) {
   for (auto& e : d->timing_events) (void)hipEventDestroy(e);
   if (d->owned && d->base) (void)hipFree(d->base);
   delete d;
+}
+
+// ---------------------------------------------------------- output path
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  int32_t nx, ny, nz, prec;
+  int64_t step, shifts;
+  double dx, dt;
+  int64_t zero;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+constexpr char kCkptMagic[8] = {'P', 'F', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr size_t kCkptChunk = (size_t)64 << 20;  // host staging per transfer
+
+struct FileCloser {
+  FILE* f;
+  ~FileCloser() {
+    if (f) std::fclose(f);
+  }
+};
+
+}  // namespace
+
+pf_status pf_checkpoint_save(pf_domain* d, const char* path) {
+  if (!d || !path) return fail(PF_ERR_INVALID_ARG, "null argument");
+  if (!d->fields_set) return fail(PF_ERR_STATE, "pf_init_fields has not been called");
+  pf_status st;
+  DevDomain cur;
+  if ((st = fetch_state(d, cur)) != PF_OK) return st;
+  const pf_domain_desc& g = d->desc;
+  const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+  FileCloser fc{std::fopen(path, "wb")};
+  if (!fc.f) return fail(PF_ERR_IO, std::string("cannot open ") + path + " for writing");
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.nx = g.nx;
+  h.ny = g.ny;
+  h.nz = g.nz;
+  h.prec = g.prec;
+  h.step = cur.step;
+  h.shifts = cur.shifts;
+  h.dx = g.dx;
+  h.dt = d->dt;
+  // stage the rounded fields in the copy that does not hold the state
+  float* stage = reinterpret_cast<float*>(d->fields(cur.parity ^ 1));
+  PF_HIP(launch_ckpt_pack(d->dev, g.prec, cells, cur.parity, stage, d->stream));
+  PF_HIP(hipStreamSynchronize(d->stream));
+  const auto write_all = [&]() -> pf_status {
+    if (std::fwrite(&h, sizeof(h), 1, fc.f) != 1) return fail(PF_ERR_IO, "checkpoint write failed");
+    const size_t total = sizeof(float) * NFIELD * (size_t)cells;
+    std::vector<char> buf(std::min(total, kCkptChunk));
+    for (size_t o = 0; o < total; o += buf.size()) {
+      const size_t n = std::min(buf.size(), total - o);
+      PF_HIP(hipMemcpy(buf.data(), reinterpret_cast<char*>(stage) + o, n, hipMemcpyDeviceToHost));
+      if (std::fwrite(buf.data(), 1, n, fc.f) != n) return fail(PF_ERR_IO, "checkpoint write failed");
+    }
+    const int rc = std::fclose(fc.f);
+    fc.f = nullptr;
+    return rc == 0 ? PF_OK : fail(PF_ERR_IO, "checkpoint write failed");
+  };
+  st = write_all();
+  // the staging block covered the ghost planes of that copy: restore them
+  // whatever the outcome of the write
+  if (d->host.top_bc) {
+    PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
+    PF_HIP(hipStreamSynchronize(d->stream));
+  }
+  return st;
+}
+
+pf_status pf_checkpoint_load(pf_domain* d, const char* path) {
+  if (!d || !path) return fail(PF_ERR_INVALID_ARG, "null argument");
+  if (!d->params_set) return fail(PF_ERR_STATE, "pf_set_params has not been called");
+  if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
+  const pf_domain_desc& g = d->desc;
+  FileCloser fc{std::fopen(path, "rb")};
+  if (!fc.f) return fail(PF_ERR_IO, std::string("cannot open ") + path);
+  CkptHeader h{};
+  if (std::fread(&h, sizeof(h), 1, fc.f) != 1) return fail(PF_ERR_IO, "checkpoint header short");
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0)
+    return fail(PF_ERR_INVALID_ARG, "not a checkpoint file");
+  if (h.nx != g.nx || h.ny != g.ny || h.nz != g.nz)
+    return fail(PF_ERR_INVALID_ARG, "checkpoint size differs from the domain");
+  if (h.step < 0) return fail(PF_ERR_INVALID_ARG, "checkpoint step is negative");
+  pf_status st;
+  DevDomain cur;
+  if ((st = fetch_state(d, cur)) != PF_OK) return st;
+  const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+  // read into copy 1, widen into copy 0, which then holds the state
+  float* stage = reinterpret_cast<float*>(d->fields(1));
+  const size_t total = sizeof(float) * NFIELD * (size_t)cells;
+  std::vector<char> buf(std::min(total, kCkptChunk));
+  for (size_t o = 0; o < total; o += buf.size()) {
+    const size_t n = std::min(buf.size(), total - o);
+    if (std::fread(buf.data(), 1, n, fc.f) != n) return fail(PF_ERR_IO, "checkpoint data short");
+    PF_HIP(hipMemcpy(reinterpret_cast<char*>(stage) + o, buf.data(), n, hipMemcpyHostToDevice));
+  }
+  DevDomain& hd = d->host;
+  hd.step = h.step;
+  hd.parity = 0;
+  hd.shifts = h.shifts;
+  hd.shift_now = 0;
+  hd.steps_left = -1;
+  if ((st = upload_desc(d)) != PF_OK) return st;
+  PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
+                        sizeof(uint32_t), d->stream));
+  PF_HIP(launch_ckpt_unpack(d->dev, g.prec, cells, 0, stage, d->stream));
+  if (hd.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
+  PF_HIP(hipStreamSynchronize(d->stream));
+  d->fields_set = true;
+  d->since_diag = 0;
+  d->diag_pending = false;
+  return PF_OK;
+}
+
+pf_status pf_mesh_phase(pf_domain* d, int32_t phase, double iso, const pf_device_buffer* out,
+                        int64_t* ntri) {
+  if (!d || !out || !ntri) return fail(PF_ERR_INVALID_ARG, "null argument");
+  if (phase < 0 || phase >= NP) return fail(PF_ERR_INVALID_ARG, "phase must be 0..3");
+  if (!std::isfinite(iso)) return fail(PF_ERR_INVALID_ARG, "iso must be finite");
+  if (out->bytes > 0 && (!out->base || reinterpret_cast<uintptr_t>(out->base) % 4 != 0))
+    return fail(PF_ERR_INVALID_ARG, "mesh buffer null or misaligned");
+  if (!d->fields_set) return fail(PF_ERR_STATE, "pf_init_fields has not been called");
+  pf_status st;
+  DevDomain cur;
+  if ((st = fetch_state(d, cur)) != PF_OK) return st;
+  const pf_domain_desc& g = d->desc;
+  const int64_t cubes = (int64_t)g.nx * g.ny * (int64_t)(g.nz - 1);
+  const int64_t cap = (int64_t)(out->bytes / (9 * sizeof(float)));
+  auto* count = reinterpret_cast<unsigned long long*>(d->base + d->L.off_mesh);
+  PF_HIP(hipMemsetAsync(count, 0, sizeof(*count), d->stream));
+  if (cubes > 0)
+    PF_HIP(launch_mesh(d->dev, g.prec, cubes, phase, iso, static_cast<float*>(out->base), cap,
+                       count, d->stream));
+  unsigned long long n = 0;
+  PF_HIP(hipMemcpyAsync(&n, count, sizeof(n), hipMemcpyDeviceToHost, d->stream));
+  PF_HIP(hipStreamSynchronize(d->stream));
+  *ntri = (int64_t)n;
+  if ((int64_t)n > cap)
+    return fail(PF_ERR_INVALID_ARG, "mesh needs " + std::to_string(n) + " triangles, buffer holds " +
+                                        std::to_string(cap));
+  return PF_OK;
 }
 
 }  // extern "C"
