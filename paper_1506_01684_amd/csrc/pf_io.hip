@@ -9,7 +9,8 @@
 // file.  Loading reverses it.
 //
 // Meshes: one thread per cube of eight neighbouring cell centres (periodic
-// in x and y, open at the first and last z planes).  Corner c of the cube at
+// in x and y, open at the first and last z planes), one work group per row
+// of cubes.  Corner c of the cube at
 // (x, y, z) is the cell (x + (c & 1), y + (c >> 1 & 1), z + (c >> 2 & 1));
 // it is inside when phi_a > iso.  The triangles of each of the 256 inside
 // patterns come from a table built at compile time by this rule: on each
@@ -157,71 +158,73 @@ constexpr McTable make_table() {
 
 __constant__ McTable kMc = make_table();
 
+// One work group per row of cubes (fixed y and z), threads along x, so that
+// neighbouring lanes share corner rows and no 64-bit division is needed.
 template <typename R>
 __global__ __launch_bounds__(256) void mesh_kernel(const DevDomain* dom, int phase, double iso,
                                                    float* out, int64_t cap,
                                                    unsigned long long* count) {
   const DevDomain& d = *dom;
   const R* f = static_cast<const R*>(d.copy[d.parity]) + (int64_t)phase * d.fstride;
-  const int64_t nx = d.nx, ny = d.ny;
-  const int64_t cubes = nx * ny * (int64_t)(d.nz - 1);
+  const int nx = d.nx, ny = d.ny;
+  const int rows = ny * (d.nz - 1);
   const int lane = threadIdx.x & 63;
-  for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < cubes;
-       c0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = c0 + threadIdx.x;
-    double v[8];
-    int mask = 0;
-    int64_t x = 0, y = 0, z = 0;
-    if (c < cubes) {
-      x = c % nx;
-      const int64_t r = c / nx;
-      y = r % ny;
-      z = r / ny;
-      const int64_t xs[2] = {x, x + 1 == nx ? 0 : x + 1};
-      const int64_t ys[2] = {y * d.pitch, (y + 1 == ny ? 0 : y + 1) * d.pitch};
-      const int64_t zs[2] = {z * d.plane, (z + 1) * d.plane};
+  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int y = row % ny, z = row / ny;
+    const int64_t ys[2] = {(int64_t)y * d.pitch, (int64_t)(y + 1 == ny ? 0 : y + 1) * d.pitch};
+    const int64_t zs[2] = {(int64_t)z * d.plane, (int64_t)(z + 1) * d.plane};
+    for (int x0 = 0; x0 < nx; x0 += blockDim.x) {  // same trip count for the whole group
+      const int x = x0 + (int)threadIdx.x;
+      double v[8];
+      int mask = 0;
+      if (x < nx) {
+        const int xs[2] = {x, x + 1 == nx ? 0 : x + 1};
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        v[k] = (double)f[zs[k >> 2] + ys[(k >> 1) & 1] + xs[k & 1]];
-        mask |= (v[k] > iso ? 1 : 0) << k;
+        for (int k = 0; k < 8; ++k) {
+          v[k] = (double)f[zs[k >> 2] + ys[(k >> 1) & 1] + xs[k & 1]];
+          mask |= (v[k] > iso ? 1 : 0) << k;
+        }
       }
-    }
-    const int n = kMc.c[mask].n;  // 0 for masks 0 and 255
-    // exclusive prefix of n over the wave, one atomic add per wave
-    int pre = n;
+      // most waves cross no surface: leave before the table and the scan
+      if (__ballot(mask != 0 && mask != 255) == 0) continue;
+      const int n = kMc.c[mask].n;  // 0 for masks 0 and 255, and for idle lanes
+      // exclusive prefix of n over the wave, one atomic add per wave
+      int pre = n;
 #pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-      const int o = __shfl_up(pre, s, 64);
-      if (lane >= s) pre += o;
-    }
-    const int total = __shfl(pre, 63, 64);
-    pre -= n;
-    unsigned long long base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(count, (unsigned long long)total);
-    base = __shfl(base, 63, 64);
-    for (int t = 0; t < n; ++t) {
-      const int64_t slot = (int64_t)base + pre + t;
-      if (slot >= cap) break;
-      float* o = out + 9 * slot;
+      for (int s = 1; s < 64; s <<= 1) {
+        const int o = __shfl_up(pre, s, 64);
+        if (lane >= s) pre += o;
+      }
+      const int total = __shfl(pre, 63, 64);
+      if (total == 0) continue;  // uniform over the wave
+      pre -= n;
+      unsigned long long base = 0;
+      if (lane == 63) base = atomicAdd(count, (unsigned long long)total);
+      base = __shfl(base, 63, 64);
+      for (int t = 0; t < n; ++t) {
+        const int64_t slot = (int64_t)base + pre + t;
+        if (slot >= cap) break;
+        float* o = out + 9 * slot;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int e = kMc.c[mask].e[3 * t + q];
-        const int a = kEdge[e][0], b = kEdge[e][1];
-        const double tt = (iso - v[a]) / (v[b] - v[a]);
-        const int axis = e >> 2;
-        const double p[3] = {(double)(x + (a & 1)), (double)(y + ((a >> 1) & 1)),
-                             (double)(z + ((a >> 2) & 1))};
-        o[3 * q + 0] = (float)(axis == 0 ? p[0] + tt : p[0]);
-        o[3 * q + 1] = (float)(axis == 1 ? p[1] + tt : p[1]);
-        o[3 * q + 2] = (float)(axis == 2 ? p[2] + tt : p[2]);
+        for (int q = 0; q < 3; ++q) {
+          const int e = kMc.c[mask].e[3 * t + q];
+          const int a = kEdge[e][0], b = kEdge[e][1];
+          const double tt = (iso - v[a]) / (v[b] - v[a]);
+          const int axis = e >> 2;
+          const double p[3] = {(double)(x + (a & 1)), (double)(y + ((a >> 1) & 1)),
+                               (double)(z + ((a >> 2) & 1))};
+          o[3 * q + 0] = (float)(axis == 0 ? p[0] + tt : p[0]);
+          o[3 * q + 1] = (float)(axis == 1 ? p[1] + tt : p[1]);
+          o[3 * q + 2] = (float)(axis == 2 ? p[2] + tt : p[2]);
+        }
       }
     }
   }
 }
 
-hipError_t launch_mesh(const DevDomain* dom, int prec, int64_t cubes, int phase, double iso,
+hipError_t launch_mesh(const DevDomain* dom, int prec, int64_t rows, int phase, double iso,
                        float* out, int64_t cap, unsigned long long* count, hipStream_t s) {
-  const int grid = grid_for(cubes);
+  const int grid = (int)(rows < 16384 ? (rows > 0 ? rows : 1) : 16384);
   if (prec == 0)
     mesh_kernel<double><<<grid, 256, 0, s>>>(dom, phase, iso, out, cap, count);
   else

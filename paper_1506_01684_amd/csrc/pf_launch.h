@@ -46,13 +46,13 @@ hipError_t launch_diag(const DevDomain* dom, int prec, int nx, int ny, int nz, d
 // Output path (pf_io.hip).  Checkpoints: the six fields of copy `src`
 // rounded to float into out[f][z][y][x] (cells = nx ny nz), and back into
 // copy `dst`.  Meshes: marching cubes of phi_phase = iso over the current
-// copy; triangles (9 floats each) go to out[0 .. cap), *count (device,
-// zeroed by the caller) receives the total.
+// copy, rows = ny (nz - 1) rows of cubes; triangles (9 floats each) go to
+// out[0 .. cap), *count (device, zeroed by the caller) receives the total.
 hipError_t launch_ckpt_pack(const DevDomain* dom, int prec, int64_t cells, int src, float* out,
                             hipStream_t s);
 hipError_t launch_ckpt_unpack(const DevDomain* dom, int prec, int64_t cells, int dst,
                               const float* in, hipStream_t s);
-hipError_t launch_mesh(const DevDomain* dom, int prec, int64_t cubes, int phase, double iso,
+hipError_t launch_mesh(const DevDomain* dom, int prec, int64_t rows, int phase, double iso,
                        float* out, int64_t cap, unsigned long long* count, hipStream_t s);
 
 }  // namespace pfk

@@ -854,12 +854,12 @@ pf_status pf_mesh_phase(pf_domain* d, int32_t phase, double iso, const pf_device
   DevDomain cur;
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
   const pf_domain_desc& g = d->desc;
-  const int64_t cubes = (int64_t)g.nx * g.ny * (int64_t)(g.nz - 1);
+  const int64_t rows = (int64_t)g.ny * (int64_t)(g.nz - 1);  // < 2^31: the layout limits items
   const int64_t cap = (int64_t)(out->bytes / (9 * sizeof(float)));
   auto* count = reinterpret_cast<unsigned long long*>(d->base + d->L.off_mesh);
   PF_HIP(hipMemsetAsync(count, 0, sizeof(*count), d->stream));
-  if (cubes > 0)
-    PF_HIP(launch_mesh(d->dev, g.prec, cubes, phase, iso, static_cast<float*>(out->base), cap,
+  if (rows > 0)
+    PF_HIP(launch_mesh(d->dev, g.prec, rows, phase, iso, static_cast<float*>(out->base), cap,
                        count, d->stream));
   unsigned long long n = 0;
   PF_HIP(hipMemcpyAsync(&n, count, sizeof(n), hipMemcpyDeviceToHost, d->stream));
