@@ -39,6 +39,7 @@ class Request:
     solid_height: int
     keep_fields: bool = False
     host_state: tuple | None = None  # (phi, mu) instead of a Voronoi state
+    cancel_at: float | None = None   # withdrawn at this time (seconds after the start)
 
 
 @dataclasses.dataclass
@@ -125,6 +126,14 @@ class GpuBackend:
             del buf
         return diag, fields, err
 
+    def cancel(self, r: Request):
+        """Drop an admitted request before it finishes: it leaves its pack
+        at this round boundary and its memory is freed."""
+        dom, buf = self.handles.pop(r.id)
+        self.packs[r.prec].remove(dom)
+        dom.close()
+        del buf
+
     def shutdown(self):
         for pk in self.packs.values():
             pk.close()
@@ -164,6 +173,9 @@ class SimBackend:
     def close(self, r: Request):
         del self.left[r.id], self.cells[r.id], self.prec_of[r.id]
         return {"nonfinite": 0}, None, ""
+
+    def cancel(self, r: Request):
+        del self.left[r.id], self.cells[r.id], self.prec_of[r.id]
 
     def shutdown(self):
         pass
@@ -242,6 +254,24 @@ class Server:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
+            # withdrawn requests: queued ones leave the queue, admitted ones
+            # leave their pack at this round boundary; others are unaffected
+            for r in [q for q in queue if q.cancel_at is not None and q.cancel_at <= now]:
+                queue.remove(r)
+                results.append(Result(r.id, r.arrival, now, now, int(np.prod(r.shape)), r.steps,
+                                      r.prec, False, "cancelled"))
+            for i in [i for i, a in active.items()
+                      if a[0].cancel_at is not None and a[0].cancel_at <= now]:
+                r, adm, need, left = active.pop(i)
+                try:
+                    self.b.cancel(r)
+                    err = f"cancelled with {left} steps left"
+                except Exception as e:
+                    err = f"cancel failed: {e}"
+                used -= need
+                results.append(Result(r.id, r.arrival, adm, now, int(np.prod(r.shape)),
+                                      r.steps - left, r.prec, False, err))
+                self.events.append(("cancel", r.id, now, used))
             # admission in arrival order (or, with "sjf", by expected service
             # time minus time waited); with backfill, later requests that fit
             # may pass a head request that does not

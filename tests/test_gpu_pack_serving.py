@@ -147,3 +147,29 @@ def test_server_isolates_a_failing_request():
         assert r.ok
         a = alone[r.id]
         assert np.array_equal(r.fields[0], a.fields[0]) and np.array_equal(r.fields[1], a.fields[1])
+
+
+def test_server_cancellation_leaves_others_unchanged():
+    """A request withdrawn early (in the queue or after its first round)
+    ends as cancelled; every other request's fields are bitwise those of its
+    run alone."""
+    import dataclasses
+
+    from paper_1506_01684_amd.serving import GpuBackend, Server, run_serial_gpu
+
+    lib().set_variant(1)
+    reqs = _requests(6, 23)
+    reqs[1] = dataclasses.replace(reqs[1], steps=400, cancel_at=reqs[1].arrival + 1e-6)
+    be = GpuBackend(max_domains=8)
+    res = Server(be, budget_bytes=64e9, max_slots=8, round_steps=5).run(reqs)
+    be.shutdown()
+    log("case cancel: " + ", ".join(f"{r.id}:{'ok' if r.ok else r.error}" for r in res))
+    assert not res[1].ok and res[1].error.startswith("cancelled")
+    good = [r for r in reqs if r.id != 1]
+    alone = {r.id: r for r in run_serial_gpu(good)}
+    for r in res:
+        if r.id == 1:
+            continue
+        assert r.ok
+        a = alone[r.id]
+        assert np.array_equal(r.fields[0], a.fields[0]) and np.array_equal(r.fields[1], a.fields[1])

@@ -129,3 +129,29 @@ def test_sjf_ages_long_jobs_in():
 def test_unknown_policy_is_rejected():
     with pytest.raises(ValueError):
         Server(SimBackend(VirtualClock()), policy="lifo")
+
+
+def test_cancelled_requests_leave_queue_and_pack():
+    """One request withdrawn while it waits in the queue, one after it was
+    admitted: both end as cancelled (the second with the steps it had done),
+    the queued one is never opened, their memory is released at once, and
+    every other request still finishes."""
+    import dataclasses
+
+    reqs = _trace(20)
+    reqs[3] = dataclasses.replace(reqs[3], cancel_at=reqs[3].arrival)  # gone on arrival
+    s0, _, first = _run(list(_trace(20)), budget_bytes=2e9, max_slots=3, round_steps=20)
+    mid = next(r for r in first if r.id == 8)
+    reqs[8] = dataclasses.replace(reqs[8], cancel_at=0.5 * (mid.admitted + mid.finished))
+    s, b, res = _run(reqs, budget_bytes=2e9, max_slots=3, round_steps=20)
+    by = {r.id: r for r in res}
+    assert [r.id for r in res] == sorted(r.id for r in reqs)
+    assert not by[3].ok and by[3].error == "cancelled" and 3 not in b.opened
+    assert not by[8].ok and by[8].error.startswith("cancelled with")
+    assert 0 < by[8].steps < reqs[8].steps
+    assert all(r.ok for r in res if r.id not in (3, 8))
+    ev = [e for e in s.events if e[0] == "cancel"]
+    assert [e[1] for e in ev] == [8]
+    before = [e for e in s.events if e[2] <= ev[0][2] and e[0] != "cancel"][-1]
+    assert ev[0][3] < before[3]  # its bytes were released
+    assert b.left == {} and b.cells == {}
