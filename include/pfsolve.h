@@ -238,7 +238,10 @@ pf_status pf_checkpoint_save(pf_domain* d, const char* path);
  * fields widened from float, step and window shifts from the header, so
  * t = step dt with this domain's dt.  Synchronises.  INVALID_ARG for a NULL
  * argument, a header that is not a checkpoint or a size mismatch, STATE
- * before pf_set_params, IO if the file cannot be read in full. */
+ * before pf_set_params or for a pack member, IO if the file cannot be
+ * opened or its length is not header + 24 bytes per cell (the state is then
+ * untouched) or a read fails part way (the state is then undefined until
+ * the next successful load or pf_init_fields). */
 pf_status pf_checkpoint_load(pf_domain* d, const char* path);
 
 /* Triangle mesh of the interface of phase `phase` (0..3): the surface

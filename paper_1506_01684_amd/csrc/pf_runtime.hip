@@ -811,10 +811,15 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path) {
   if (h.nx != g.nx || h.ny != g.ny || h.nz != g.nz)
     return fail(PF_ERR_INVALID_ARG, "checkpoint size differs from the domain");
   if (h.step < 0) return fail(PF_ERR_INVALID_ARG, "checkpoint step is negative");
+  const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+  // a truncated file is refused before any field is touched
+  if (std::fseek(fc.f, 0, SEEK_END) != 0 || std::ftell(fc.f) != (long)(sizeof(CkptHeader) +
+                                                                      sizeof(float) * NFIELD * cells) ||
+      std::fseek(fc.f, (long)sizeof(CkptHeader), SEEK_SET) != 0)
+    return fail(PF_ERR_IO, "checkpoint file has the wrong length");
   pf_status st;
   DevDomain cur;
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
-  const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
   // read into copy 1, widen into copy 0, which then holds the state
   float* stage = reinterpret_cast<float*>(d->fields(1));
   const size_t total = sizeof(float) * NFIELD * (size_t)cells;

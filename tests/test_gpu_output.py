@@ -204,9 +204,12 @@ def test_checkpoint_errors():
         assert "INVALID_ARG" in str(e.value)
         short = os.path.join(tmp, "short.pfc")
         open(short, "wb").write(open(path, "rb").read()[:1000])
+        before = d.read()
         with pytest.raises(pf.PfError) as e:
             d.load_checkpoint(short)
         assert "IO" in str(e.value)
+        after = d.read()  # a truncated file leaves the state alone
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
         fresh = pf.Domain(shape, "fp64")
         with pytest.raises(pf.PfError) as e:
             fresh.load_checkpoint(path)  # no parameters yet
