@@ -216,6 +216,21 @@ __device__ __forceinline__ void phi_face(const KP& P, const R pb[NP], const R gn
   }
 }
 
+// Contributions of one phi face to the A_a of its two cells (A_a = half the
+// sum of the six face shares minus the flux differences over dx): to the
+// cell below the face, whose upper face it is, P_a = S_a/2 - F_a/dx; to the
+// cell above, Q_a = S_a/2 + F_a/dx.  Each rounding is spelled out.
+template <typename R>
+__device__ __forceinline__ void face_pq(const R F[NP], const R S[NP], R inv_dx, R Pv[NP], R Qv[NP]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    const R h = R(0.5) * S[a];
+    Pv[a] = fma_(-F[a], inv_dx, h);
+    Qv[a] = fma_(F[a], inv_dx, h);
+  }
+}
+
 // Exact shortcut tests (the paper's shortcuts, Sec. 3.3, restricted to work
 // whose result is known exactly).
 //
@@ -227,16 +242,15 @@ __device__ __forceinline__ bool zero_normal(const R gn[NP]) {
   return gn[0] == R(0) && gn[1] == R(0) && gn[2] == R(0) && gn[3] == R(0);
 }
 
-// A pure cell (phi = e_a exactly) whose face sums vanish has A = 0, a zero
+// A pure cell (phi = e_a exactly) with A = 0 (as when its faces vanish) has a zero
 // driving force and obstacle derivative 16/pi^2 gamma_ab for the absent
 // phases; when its plane marks e_a as a fixed point of the Euler step and
 // the projection (fixed_mask bit a), its new value is e_a again.
 template <typename R>
-__device__ __forceinline__ bool pure_cell_fixed(const R ph[NP], const R Ss[NP], const R Fd[NP],
-                                                int fixed_mask) {
+__device__ __forceinline__ bool pure_cell_fixed(const R ph[NP], const R A[NP], int fixed_mask) {
 #pragma unroll
   for (int a = 0; a < NP; ++a)
-    if (Ss[a] != R(0) || Fd[a] != R(0)) return false;
+    if (A[a] != R(0)) return false;
   const int a1 = ph[0] == R(1) ? 0 : (ph[1] == R(1) ? 1 : (ph[2] == R(1) ? 2 : (ph[3] == R(1) ? 3 : -1)));
   if (a1 < 0) return false;
   int nonzero = 0;
@@ -285,14 +299,11 @@ __device__ __forceinline__ void project_simplex(const double y[NP], double x[NP]
 // obstacle derivative, the driving force (2 phi_a/S)(psi_a - sum h_b psi_b),
 // rhs_a = eps T A_a + (T/eps) omega'_a + psi'_a, Lagrange mean over the four
 // phases, explicit Euler, projection.
-//   Ssum[a] = sum over directions of (S_up + S_low)
-//   Fdiff[a] = sum over directions of (F_up - F_low)
+//   A[a] = 1/2 sum over the six faces of S - sum over directions of
+//          (F_up - F_low) / dx
 template <typename R, typename KP, typename CP>
 __device__ __forceinline__ void phi_cell(const KP& P, const CP& C, const R ph[NP], const R mu[NM],
-                                         const R Ssum[NP], const R Fdiff[NP], double out[NP]) {
-  R A[NP];
-#pragma unroll
-  for (int a = 0; a < NP; ++a) A[a] = R(0.5) * Ssum[a] - Fdiff[a] * (R)P.inv_dx;
+                                         const R A[NP], double out[NP]) {
   R S = ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2] + ph[3] * ph[3];
   R invS = rcp_(S);
   R psi[NP], psibar = R(0);

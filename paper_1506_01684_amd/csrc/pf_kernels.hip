@@ -290,8 +290,11 @@ __global__ __launch_bounds__(kTileThreads) void phi_direct_kernel(DevDomain* con
       for (int a = 0; a < NP; ++a) pc[a] = ph[a][o];
       mc[0] = mu[0][o];
       mc[1] = mu[1][o];
+      R A[NP];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) A[a] = R(0.5) * Ss[a] - Fd[a] * (R)P.inv_dx;
       double out[NP];
-      phi_cell<R>(P, tab[k], pc, mc, Ss, Fd, out);
+      phi_cell<R>(P, tab[k], pc, mc, A, out);
 #pragma unroll
       for (int a = 0; a < NP; ++a) dst[a * fs + o] = (R)out[a];
     }

@@ -20,6 +20,10 @@
 // faces cannot carry the anti-trapping current (no liquid, or only liquid,
 // around them; classified by the phi-sweep) go to a lighter kernel that
 // stages one phi^n plane and no phi^{n+1} neighbours.
+// In the phi-sweep a face enters its two cells' A_a through two shares
+// (face_pq): the one for the cell below the face stays in the registers of
+// the thread that evaluated it, only the one for the cell above goes
+// through LDS, which halves the face buffers.
 // LDS layout avoids bank conflicts: phi is stored as 16-byte vectors
 // (two doubles or four floats per lane access) and face values as
 // structure of arrays (consecutive lanes touch consecutive words).
@@ -315,8 +319,8 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
   constexpr int NSLOT = ANISO ? 3 : 1;
   constexpr int AHEAD = ANISO ? 2 : 1;  // plane loaded during iteration k: k + AHEAD
   __shared__ LdsPhi<R, NSLOT> s_phi;
-  __shared__ R s_fx[2 * NP][kMaxFx];  // F[0..3], S[0..3] of x faces
-  __shared__ R s_fy[2 * NP][kMaxFy];
+  __shared__ R s_qx[NP][kMaxFx];  // Q of the x faces (their share in the cell above)
+  __shared__ R s_qy[NP][kMaxFy];
   __shared__ uint8_t s_jw[4];          // per-wave bytes of the item's classification word
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
@@ -359,9 +363,9 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
     V4<R> own_k = load4<R>(src, g.zc(kstart), G.own_b);
     __syncthreads();
 
-    R Fzl[NP], Szl[NP];  // z face below the current plane
+    R Qzl[NP];  // share of the z face below the current plane
 #pragma unroll
-    for (int a = 0; a < NP; ++a) Fzl[a] = Szl[a] = R(0);
+    for (int a = 0; a < NP; ++a) Qzl[a] = R(0);
 
     for (int k = kstart; k < G.z1; ++k) {
       const bool cells = k >= G.z0;  // kstart only evaluates the z face above it
@@ -372,6 +376,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       V4<R> nxt_halo;
       if (G.halo_c >= 0) nxt_halo = load4<R>(src, pa, G.halo_b);
       R mc[NM] = {R(0), R(0)};
+      R Px[NP] = {}, Py[NP] = {};  // shares of the own upper x and y faces
       if (cells) {
         mc[0] = ldg<R>(src.at(4, k), G.own_b);
         mc[1] = ldg<R>(src.at(5, k), G.own_b);
@@ -394,10 +399,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
             if constexpr (ANISO) lds_face_tangential<R, 0>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
             phi_face<R, ANISO, 0>(P, pb, gn, gt1, gt2, F, S);
           }
+          R Pv[NP], Qv[NP];
+          face_pq<R>(F, S, inv_dx, Pv, Qv);
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
-            s_fx[a][fo] = F[a];
-            s_fx[NP + a][fo] = S[a];
+            s_qx[a][fo] = Qv[a];
+            if (!edge) Px[a] = Pv[a];
           }
         }
 #pragma unroll 1
@@ -412,16 +419,19 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
             if constexpr (ANISO) lds_face_tangential<R, 1>(s_phi, G, cx, cy, sm, s0, sp, inv_4dx, gt1, gt2);
             phi_face<R, ANISO, 1>(P, pb, gn, gt1, gt2, F, S);
           }
+          R Pv[NP], Qv[NP];
+          face_pq<R>(F, S, inv_dx, Pv, Qv);
 #pragma unroll
           for (int a = 0; a < NP; ++a) {
-            s_fy[a][fo] = F[a];
-            s_fy[NP + a][fo] = S[a];
+            s_qy[a][fo] = Qv[a];
+            if (!edge) Py[a] = Pv[a];
           }
         }
       }
       // z face above plane k (zero on the z boundaries)
-      R Fzu[NP] = {}, Szu[NP] = {};
+      R Pz[NP] = {}, Qzu[NP] = {};
       if (g.zface(k)) {
+        R Fzu[NP] = {}, Szu[NP] = {};
         R pb[NP], gn[NP], gt1[NP] = {}, gt2[NP] = {};
         if constexpr (ANISO) {
           lds_face_normal<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, s0, sp, inv_dx, pb, gn);
@@ -438,6 +448,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
             lds_face_tangential<R, 2>(s_phi, G, G.lx + 1, G.ly + 1, sm, s0, sp, inv_4dx, gt1, gt2);
           phi_face<R, ANISO, 2>(P, pb, gn, gt1, gt2, Fzu, Szu);
         }
+        face_pq<R>(Fzu, Szu, inv_dx, Pz, Qzu);
       }
       V4<R> ownv;
       if constexpr (ANISO) ownv = s_phi.get(s0, G.own_c);
@@ -453,35 +464,24 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
         }
       }
       if (cells && G.valid) {
-        const int fl = G.ly * (G.tx + 1) + G.lx;  // lower x face; upper is fl+1
-        const int yl = G.ly * G.tx + G.lx;        // lower y face; upper is yl+tx
-        R Ss[NP], Fd[NP];
+        const int fl = G.ly * (G.tx + 1) + G.lx;  // lower x face
+        const int yl = G.ly * G.tx + G.lx;        // lower y face
+        R A[NP];
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-          Ss[a] = R(0);
-          Fd[a] = R(0);
-          Ss[a] += s_fx[NP + a][fl + 1] + s_fx[NP + a][fl];
-          Fd[a] += s_fx[a][fl + 1] - s_fx[a][fl];
-          Ss[a] += s_fy[NP + a][yl + G.tx] + s_fy[NP + a][yl];
-          Fd[a] += s_fy[a][yl + G.tx] - s_fy[a][yl];
-          Ss[a] += Szu[a] + Szl[a];
-          Fd[a] += Fzu[a] - Fzl[a];
-        }
+        for (int a = 0; a < NP; ++a)
+          A[a] = ((Px[a] + s_qx[a][fl]) + (Py[a] + s_qy[a][yl])) + (Pz[a] + Qzl[a]);
         double out[NP];
-        if (shortcut && pure_cell_fixed(ownv.v, Ss, Fd, X.tab[k].pure_fixed)) {
+        if (shortcut && pure_cell_fixed(ownv.v, A, X.tab[k].pure_fixed)) {
 #pragma unroll
           for (int a = 0; a < NP; ++a) out[a] = (double)ownv.v[a];
         } else {
-          phi_cell<R>(P, X.tab[k], ownv.v, mc, Ss, Fd, out);
+          phi_cell<R>(P, X.tab[k], ownv.v, mc, A, out);
         }
 #pragma unroll
         for (int a = 0; a < NP; ++a) stg<R>(dst.at(a, k), G.own_b, (R)out[a]);
       }
 #pragma unroll
-      for (int a = 0; a < NP; ++a) {
-        Fzl[a] = Fzu[a];
-        Szl[a] = Szu[a];
-      }
+      for (int a = 0; a < NP; ++a) Qzl[a] = Qzu[a];
       if constexpr (!ANISO) own_k = nxt_own;
       __syncthreads();  // B2: LDS plane and faces consumed
     }
