@@ -313,9 +313,8 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
 // ============================================================ phi-sweep
 
 template <typename R, bool ANISO>
-__global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* const* doms,
-                                                                 const int32_t* first, int ndom,
-                                                                 int total) {
+__device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int32_t* first,
+                                               int ndom, int total) {
   constexpr int NSLOT = ANISO ? 3 : 1;
   constexpr int AHEAD = ANISO ? 2 : 1;  // plane loaded during iteration k: k + AHEAD
   __shared__ LdsPhi<R, NSLOT> s_phi;
@@ -499,6 +498,29 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_kernel(DevDomain* cons
       }
     }
   }
+}
+
+// One kernel per precision and stencil.  The FP32 anisotropic sweep, which
+// is bound by its arithmetic, is held to 96 VGPRs so that five waves fit per
+// SIMD (it needs 98 otherwise, which allows four).
+__global__ __launch_bounds__(kTileThreads) void phi_tiled_f64(DevDomain* const* doms,
+                                                              const int32_t* first, int ndom,
+                                                              int total) {
+  phi_tiled_body<double, false>(doms, first, ndom, total);
+}
+__global__ __launch_bounds__(kTileThreads) void phi_tiled_f64_aniso(DevDomain* const* doms,
+                                                                    const int32_t* first, int ndom,
+                                                                    int total) {
+  phi_tiled_body<double, true>(doms, first, ndom, total);
+}
+__global__ __launch_bounds__(kTileThreads) void phi_tiled_f32(DevDomain* const* doms,
+                                                              const int32_t* first, int ndom,
+                                                              int total) {
+  phi_tiled_body<float, false>(doms, first, ndom, total);
+}
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(5))) void
+phi_tiled_f32_aniso(DevDomain* const* doms, const int32_t* first, int ndom, int total) {
+  phi_tiled_body<float, true>(doms, first, ndom, total);
 }
 
 // ============================================================= mu-sweep
@@ -961,14 +983,14 @@ hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_
   const int grid = L.total;
   if (prec == 0) {
     if (aniso)
-      phi_tiled_kernel<double, true><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f64_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     else
-      phi_tiled_kernel<double, false><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   } else {
     if (aniso)
-      phi_tiled_kernel<float, true><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f32_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     else
-      phi_tiled_kernel<float, false><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   }
   return hipGetLastError();
 }

@@ -27,7 +27,7 @@ def test_traffic_is_used_only_for_matching_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(root))
     assert bench.kernel_source_digest() == digest
     assert bench.recorded_traffic("mu_tiled_f64", "c2") == (100.0 * 2.0 + 50.0) * 1024.0
-    assert bench.recorded_traffic("phi_tiled_kernel<double, false>", "c2") is None
+    assert bench.recorded_traffic("phi_tiled_f64", "c2") is None
     # a changed device source invalidates the record
     src = root / "paper_1506_01684_amd" / "csrc" / "pf_tiled.hip"
     src.write_text(src.read_text() + "\n// changed\n")
