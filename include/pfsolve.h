@@ -148,6 +148,13 @@ typedef struct {
                            * direct variant, with the shortcuts off, and
                            * before the first step                         */
   int32_t work_items;     /* work items per sweep of this domain           */
+  int32_t fixed_items;    /* work items of the last step whose phi the
+                           * tiled sweep copied unchanged: every cell in and
+                           * around them held one pure phase that its planes
+                           * mark as a fixed point (Sec. 3.3 bulk shortcut,
+                           * exact); 0 with the shortcuts off, the direct
+                           * variant, and before the first step           */
+  int32_t reserved;
 } pf_diag;
 
 /* Device bytes a domain needs (both field copies, each with one extra

@@ -64,6 +64,8 @@ class PfDiag(C.Structure):
         ("window_shifts", C.c_int64),
         ("light_items", C.c_int32),
         ("work_items", C.c_int32),
+        ("fixed_items", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -108,8 +108,11 @@ struct DevDomain {
   double mu_fill[NM];         // mu of the liquid plane a shift adds / of the ghost plane
   void* copy[2];              // base of each 6-field copy
   void* coef;                 // PlaneCoef<R>[nz] of the running step
-  void* jfree;                // uint32 per work item of the tiled sweeps, then a count
-  int32_t nitems;             // work items of the tiled sweeps (index of that count)
+  void* jfree;                // uint32 per work item of the tiled sweeps, then two counts
+  int32_t nitems;             // work items of the tiled sweeps (index of those counts)
+  int32_t pflag_ok[2];        // pflag[c] describes the state held in copy c
+  void* pflag[2];             // uint8 per tile and z chunk [iz][iy][ix]: the phase all
+                              // cells of the chunk hold purely in copy c, 0xFF if none
   double dt, dx;
   double eps, TE, T0, G, v, zoff;
   double chi0[NP][NM], chi1[NP][NM], c0[NP][NM], c1[NP][NM];

@@ -44,8 +44,12 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     if (threadIdx.x == 0) d.active = 0;
     return;
   }
-  // items of this step that the phi-sweep finds free of anti-trapping faces
-  if (threadIdx.x == 0) static_cast<uint32_t*>(d.jfree)[d.nitems] = 0u;
+  // counts of this step's items that the phi-sweep finds free of
+  // anti-trapping faces, and that it copies unchanged
+  if (threadIdx.x == 0) {
+    static_cast<uint32_t*>(d.jfree)[d.nitems] = 0u;
+    static_cast<uint32_t*>(d.jfree)[d.nitems + 1] = 0u;
+  }
   // Moving window: has the front passed plane window_z?  The liquid
   // fraction of that plane of the current state is summed in FP64 (strided
   // per thread, then a fixed tree); below half the plane area the step
@@ -143,6 +147,10 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    // the pure-phase flags of the copy this step writes are renewed by the
+    // tiled phi-sweep; a shifted state invalidates those of its copy
+    d.pflag_ok[src ^ 1] = 0;
+    if (shift) d.pflag_ok[src] = 0;
     d.active = 1;
     d.cur_step = n;
     d.shift_now = shift;

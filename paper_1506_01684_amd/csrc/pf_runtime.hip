@@ -80,8 +80,9 @@ struct Layout {
   int32_t pitch;
   int64_t plane, fstride;  // elements
   size_t elem;
-  size_t off_desc, off_ptrs, off_first, off_coef, off_jfree, off_mesh, off_partials, off_diag,
-      off_map, off_fields;
+  size_t off_desc, off_ptrs, off_first, off_coef, off_jfree, off_pflag, off_mesh, off_partials,
+      off_diag, off_map, off_fields;
+  size_t pflag_bytes;
   size_t copy_bytes, total;
 };
 
@@ -118,9 +119,12 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   L.off_coef = off;
   const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
   off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
-  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and a count
-  off = align_up(off + sizeof(uint32_t) * ((size_t)choose_tiling(d.nx, d.ny, d.nz).blocks() + 1),
-                 kAlign);
+  const Tiling T = choose_tiling(d.nx, d.ny, d.nz);
+  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and two counts
+  off = align_up(off + sizeof(uint32_t) * ((size_t)T.blocks() + 2), kAlign);
+  L.pflag_bytes = align_up((size_t)T.ntx * T.nty * T.nzc, kAlign);
+  L.off_pflag = off;  // the pure-phase flags of each copy's state
+  off += 2 * L.pflag_bytes;
   L.off_mesh = off;  // triangle counter of pf_mesh_phase
   off = align_up(off + sizeof(unsigned long long), kAlign);
   L.off_partials = off;
@@ -422,6 +426,9 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
   h.coef = d->base + L.off_coef;
   h.jfree = d->base + L.off_jfree;
   h.nitems = d->T.blocks();
+  h.pflag[0] = d->base + L.off_pflag;
+  h.pflag[1] = d->base + L.off_pflag + L.pflag_bytes;
+  h.pflag_ok[0] = h.pflag_ok[1] = 0;  // the host mirror never vouches for the flags
   h.dx = desc->dx;
   int32_t first[2] = {0, d->T.blocks()};
   DevDomain* self = d->dev;
@@ -532,7 +539,7 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   if ((st = upload_desc(d)) != PF_OK) return st;
   // no step has classified the items yet
   PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
-                        sizeof(uint32_t), d->stream));
+                        2 * sizeof(uint32_t), d->stream));
   if (in->kind == PF_INIT_VORONOI) {
     if (in->nseeds < 0 || in->solid_height < 0)
       return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
@@ -704,10 +711,11 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->phi_max = v[8];
     diag->nonfinite = (int64_t)v[9];
     diag->window_shifts = cur.shifts;
-    uint32_t light = 0;
-    PF_HIP(hipMemcpy(&light, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(),
-                     sizeof(light), hipMemcpyDeviceToHost));
-    diag->light_items = (int32_t)light;
+    uint32_t counts[2] = {0, 0};
+    PF_HIP(hipMemcpy(counts, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(),
+                     sizeof(counts), hipMemcpyDeviceToHost));
+    diag->light_items = (int32_t)counts[0];
+    diag->fixed_items = (int32_t)counts[1];
     diag->work_items = d->T.blocks();
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
@@ -837,7 +845,7 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path) {
   hd.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
   PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
-                        sizeof(uint32_t), d->stream));
+                        2 * sizeof(uint32_t), d->stream));
   PF_HIP(launch_ckpt_unpack(d->dev, g.prec, cells, 0, stage, d->stream));
   if (hd.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
   PF_HIP(hipStreamSynchronize(d->stream));

@@ -262,6 +262,7 @@ struct ItemCtx {
   Copy src, dst;
   uint32_t* jf;  // the item's classification word (written by the phi-sweep)
   uint32_t* jn;  // the step's count of light items
+  DevDomain* dw;  // the descriptor, for the one word the sweeps write (pflag_ok)
 };
 
 // Item classification for the mu-sweep.  The anti-trapping current of a
@@ -278,6 +279,7 @@ struct ItemCtx {
 // of all items: each kernel's last round of items runs on a partly idle
 // chip, which a small share of light items does not repay.
 constexpr uint64_t kBulkMinPct = 60;
+constexpr uint32_t kBulkDone = 0x80000000u;  // item copied by the phi bulk shortcut
 __device__ __forceinline__ bool item_jfree(uint32_t f) {
   return ((f & (f >> 8) & (f >> 16) & (f >> 24)) & 3u) != 0;
 }
@@ -292,6 +294,7 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   const PF_CONST DevDomain& d = domain_at(doms, di);
   if (!d.active) return false;  // uniform over the work group
   const int local = item - first_item(first, di);
+  X.dw = to_const(doms)[di];
   X.jf = static_cast<uint32_t*>(d.jfree) + local;
   X.jn = static_cast<uint32_t*>(d.jfree) + d.nitems;
   if (jsel >= 0) {  // uniform over the work group
@@ -310,6 +313,92 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   return true;
 }
 
+// ------------------------------------------- bulk shortcut of the phi-sweep
+//
+// Each phi-sweep records, per tile and z chunk, the phase that all of the
+// chunk's new cells hold purely (0..3) or 0xFF, in the flags of the copy it
+// writes (pflag); the prologue withdraws a copy's flags before it is
+// rewritten or after a window shift, and the sweep vouches for them again
+// (pflag_ok) when it has written them.  A later sweep may then copy a chunk
+// unchanged when it and its 26 neighbours (periodic in x and y; at the z
+// ends the mirror adds nothing, a Dirichlet ghost is liquid) hold the same
+// pure phase and every plane of the chunk marks that phase as a fixed point:
+// every face of every cell then has zero normal differences, so each cell
+// is a pure cell with A = 0, which the per-cell shortcut keeps exactly.
+
+// Tile and chunk coordinates of an item (uniform over the group; made
+// scalar so that the lookups below stay in scalar registers).
+struct ChunkId {
+  int ix, iy, iz;
+};
+template <typename DD>
+__device__ __forceinline__ ChunkId chunk_id(const DD& d, const TileGeo& G) {
+  return {__builtin_amdgcn_readfirstlane(G.x0 / G.tx), __builtin_amdgcn_readfirstlane(G.y0 / G.ty),
+          __builtin_amdgcn_readfirstlane(G.z0 / d.zc)};
+}
+template <typename DD>
+__device__ __forceinline__ int chunk_index(const DD& d, const ChunkId& c) {
+  return (c.iz * d.nty + c.iy) * d.ntx + c.ix;  // < 2^31: the layout bounds the items
+}
+
+template <typename DD>
+__device__ __forceinline__ void dd_mark_flags(const DD& d, DevDomain* dw) {
+  // the flags of the copy being written are complete once the sweep ends
+  // (the descriptor is read through the constant address space; this one
+  // word, which the sweeps never read, is written through its plain pointer)
+  to_global(&dw->pflag_ok[d.cur_src ^ 1])[0] = 1;
+}
+
+// The phase of a bulk chunk that may be copied, or -1 (uniform over the group).
+template <typename DD, typename TAB>
+__device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, int z0, int z1,
+                                                const TAB* tab) {
+  if (!d.pflag_ok[d.cur_src]) return -1;
+  const PF_CONST uint8_t* f = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src]));
+  const int a = f[chunk_index(d, c)];
+  if (a >= NP) return -1;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int jz = c.iz + dz;
+    if (jz < 0) continue;  // mirror: the chunk's own bottom plane
+    if (jz >= d.nzc) {     // mirror, or the liquid ghost plane of a Dirichlet top
+      if (d.top_bc && a != LQ) return -1;
+      continue;
+    }
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jy = c.iy + dy < 0 ? d.nty - 1 : (c.iy + dy == d.nty ? 0 : c.iy + dy);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int jx = c.ix + dx < 0 ? d.ntx - 1 : (c.ix + dx == d.ntx ? 0 : c.ix + dx);
+        if (f[(jz * d.nty + jy) * d.ntx + jx] != a) return -1;
+      }
+    }
+  }
+  for (int k = z0; k < z1; ++k)
+    if (!((tab[k].pure_fixed >> a) & 1)) return -1;
+  return a;
+}
+
+// The phase a cell holds purely (phi = e_a exactly), or -1.
+template <typename R>
+__device__ __forceinline__ int pure_phase(const R o[NP]) {
+  int a = -1, ones = 0, zeros = 0;
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    ones += o[b] == R(1);
+    zeros += o[b] == R(0);
+    if (o[b] == R(1)) a = b;
+  }
+  return ones == 1 && zeros == NP - 1 ? a : -1;
+}
+
+// Combination over a wave of the lanes' pure phases (-2: lane wrote no
+// cell): -2 if no lane wrote, the common phase, or -1.
+__device__ __forceinline__ int wave_pure_phase(int po) {
+  if (!__any(po != -2)) return -2;
+  for (int a = 0; a < NP; ++a)
+    if (__all(po == a || po == -2)) return a;
+  return -1;
+}
+
 // ============================================================ phi-sweep
 
 template <typename R, bool ANISO>
@@ -321,6 +410,7 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
   __shared__ R s_qx[NP][kMaxFx];  // Q of the x faces (their share in the cell above)
   __shared__ R s_qy[NP][kMaxFy];
   __shared__ uint8_t s_jw[4];          // per-wave bytes of the item's classification word
+  __shared__ int8_t s_pw[4];           // per-wave pure phase of the outputs (pure_phase_flag)
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
 
@@ -335,6 +425,13 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
     const R inv_dx = (R)P.inv_dx, inv_4dx = (R)P.inv_4dx;
     const bool shortcut = P.shortcuts != 0;
     const int kstart = G.z0 - 1;
+    const PF_CONST DevDomain& dd = *X.dp;
+    const ChunkId cid = chunk_id(dd, G);
+    const int z0 = __builtin_amdgcn_readfirstlane(G.z0), z1 = __builtin_amdgcn_readfirstlane(G.z1);
+
+    // chunks copied unchanged by phi_bulk_kernel (launched just before)
+    if (*to_const(X.jf) & kBulkDone) continue;
+    int po = -2;  // pure phase of this thread's outputs so far (-2: none, -1: mixed)
 
     // liquid content of every phi^n cell this item loads (item_jfree; the
     // FP64 mu-sweep only)
@@ -476,25 +573,48 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
         } else {
           phi_cell<R>(P, X.tab[k], ownv.v, mc, A, out);
         }
+        R o[NP];
 #pragma unroll
-        for (int a = 0; a < NP; ++a) stg<R>(dst.at(a, k), G.own_b, (R)out[a]);
+        for (int a = 0; a < NP; ++a) {
+          o[a] = (R)out[a];
+          stg<R>(dst.at(a, k), G.own_b, o[a]);
+        }
+        const int pa = pure_phase(o);
+        po = po == -2 ? pa : (po == pa ? po : -1);
       }
 #pragma unroll
       for (int a = 0; a < NP; ++a) Qzl[a] = Qzu[a];
       if constexpr (!ANISO) own_k = nxt_own;
       __syncthreads();  // B2: LDS plane and faces consumed
     }
-    if constexpr (CLASSIFY) {
+    // end of the item: the pure phase of its outputs (for the next step's
+    // bulk shortcut) and, in FP64, the mu-sweep's classification
+    {
+      const int wp = wave_pure_phase(po);
       uint32_t b = 0;
-      if (shortcut && !P.mu_frozen)
-        b = !P.antitrap ? 3u : (__all(no_liq) ? 1u : 0u) | (__all(only_liq) ? 2u : 0u);
-      if (lane == 0) s_jw[wave] = (uint8_t)b;
+      if constexpr (CLASSIFY)
+        if (shortcut && !P.mu_frozen)
+          b = !P.antitrap ? 3u : (__all(no_liq) ? 1u : 0u) | (__all(only_liq) ? 2u : 0u);
+      if (lane == 0) {
+        s_pw[wave] = (int8_t)wp;
+        s_jw[wave] = (uint8_t)b;
+      }
       __syncthreads();
       if (t == 0) {
-        const uint32_t w = (uint32_t)s_jw[0] | (uint32_t)s_jw[1] << 8 | (uint32_t)s_jw[2] << 16 |
-                           (uint32_t)s_jw[3] << 24;
-        *to_global(X.jf) = w;
-        if (item_jfree(w)) atomicAdd(X.jn, 1u);
+        int ph = -2;
+        for (int w = 0; w < 4; ++w) {
+          const int v = s_pw[w];
+          ph = v == -2 ? ph : (ph == -2 || ph == v ? v : -1);
+        }
+        static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
+            ph >= 0 ? (uint8_t)ph : (uint8_t)0xFF;
+        dd_mark_flags(dd, X.dw);
+        if constexpr (CLASSIFY) {
+          const uint32_t w = (uint32_t)s_jw[0] | (uint32_t)s_jw[1] << 8 | (uint32_t)s_jw[2] << 16 |
+                             (uint32_t)s_jw[3] << 24;
+          *to_global(X.jf) = w;
+          if (item_jfree(w)) atomicAdd(X.jn, 1u);
+        }
       }
     }
   }
@@ -521,6 +641,52 @@ __global__ __launch_bounds__(kTileThreads) void phi_tiled_f32(DevDomain* const* 
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(5))) void
 phi_tiled_f32_aniso(DevDomain* const* doms, const int32_t* first, int ndom, int total) {
   phi_tiled_body<float, true>(doms, first, ndom, total);
+}
+
+// Bulk shortcut of the phi-sweep, launched before it over the same items:
+// a chunk that bulk_fixed_phase finds fixed is copied unchanged, its flags
+// and (FP64) the mu-sweep's classification are written, and its word is
+// marked kBulkDone so that the sweep passes it over; every other item's
+// word is cleared for the sweep to fill.
+template <typename R>
+__global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const* doms,
+                                                                const int32_t* first, int ndom,
+                                                                int total) {
+  const int t = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    ItemCtx<R> X;
+    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    const TileGeo& G = X.G;
+    const auto& P = kparams<R>(*X.dp);
+    const PF_CONST DevDomain& dd = *X.dp;
+    const ChunkId cid = chunk_id(dd, G);
+    const int z0 = __builtin_amdgcn_readfirstlane(G.z0), z1 = __builtin_amdgcn_readfirstlane(G.z1);
+    const int fixed = P.shortcuts ? bulk_fixed_phase(dd, cid, z0, z1, X.tab) : -1;
+    if (fixed < 0) {
+      if (t == 0) *to_global(X.jf) = 0u;
+      continue;
+    }
+    if (G.valid) {
+#pragma unroll 4
+      for (int k = G.z0; k < G.z1; ++k) {
+        const V4<R> v = load4<R>(X.src, k, G.own_b);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) stg<R>(X.dst.at(a, k), G.own_b, v.v[a]);
+      }
+    }
+    if (t == 0) {
+      static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] = (uint8_t)fixed;
+      dd_mark_flags(dd, X.dw);
+      atomicAdd(X.jn + 1, 1u);
+      uint32_t w = 0;
+      if constexpr (sizeof(R) == 8) {  // the mu-sweep's classification (item_jfree)
+        const uint32_t b = P.mu_frozen ? 0u : (!P.antitrap ? 3u : (fixed == LQ ? 2u : 1u));
+        w = b * 0x01010101u;
+        if (item_jfree(w)) atomicAdd(X.jn, 1u);
+      }
+      *to_global(X.jf) = w | kBulkDone;
+    }
+  }
 }
 
 // ============================================================= mu-sweep
@@ -981,6 +1147,10 @@ __global__ __launch_bounds__(kTileThreads) void mu_bulk_f64(DevDomain* const* do
 
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
   const int grid = L.total;
+  if (prec == 0)
+    phi_bulk_kernel<double><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+  else
+    phi_bulk_kernel<float><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   if (prec == 0) {
     if (aniso)
       phi_tiled_f64_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);

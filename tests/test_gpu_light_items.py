@@ -60,3 +60,49 @@ def test_light_items_reported_only_for_the_fp64_tiled_sweep():
             assert dg["light_items"] == 0, (prec, var)
     finally:
         pf.set_variant(1)
+
+
+@pytest.mark.parametrize("prec,aniso,top_bc", [("fp64", False, 0), ("fp32", True, 0),
+                                               ("fp64", True, 1)])
+def test_bulk_chunks_are_copied_exactly(prec, aniso, top_bc):
+    """Chunks that hold one pure phase, with all their neighbours, at a fixed
+    point are copied by the phi bulk shortcut: most of a tall liquid column
+    is; the result equals the shortcuts-off run bitwise (with the Dirichlet
+    top too, whose liquid ghost allows only liquid chunks at the top)."""
+    shape = (96, 24, 70)
+    p = pfinputs.p0_params(solid_height=10, delta_sl=0.05 if aniso else 0.0)
+    p["top_bc"] = top_bc
+    p["dt"] = oracle.default_dt(p, shape)
+    a, da = _run(shape, p, prec, 10, 1, (4, 7, 10))
+    b, db = _run(shape, p, prec, 10, 0, (4, 7, 10))
+    log(f"bulk {prec} aniso={aniso} top_bc={top_bc}: fixed items {da['fixed_items']} of "
+        f"{da['work_items']}")
+    assert da["fixed_items"] > da["work_items"] // 3 and db["fixed_items"] == 0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_bulk_flags_survive_variant_switches_and_window_shifts():
+    """Flags are only trusted when the tiled sweep wrote them for the state at
+    hand: switching to the direct variant and back, and moving-window shifts,
+    must not let a stale flag copy a chunk that changed."""
+    pf = lib()
+    shape = (64, 16, 40)
+    p = pfinputs.p0_params(solid_height=20, G=0.04, v=1.0)
+    p.update(window_z=12)  # below the front: shifts in the first steps
+    p["dt"] = oracle.default_dt(p, shape)
+    out = {}
+    try:
+        for sc in (0, 1):
+            q = dict(p, shortcuts=sc)
+            d = gpu_domain(shape, q, "fp64", 1, voronoi=(2, 5, 20))
+            for var, n in ((1, 6), (0, 3), (1, 6), (0, 1), (1, 8)):
+                pf.set_variant(var)
+                d.step(n)
+            out[sc] = (d.read(), d.diagnostics())
+            d.close()
+    finally:
+        pf.set_variant(1)
+    (a, da), (b, db) = out[1], out[0]
+    log(f"switches: shifts {da['window_shifts']}, fixed items {da['fixed_items']}")
+    assert da["window_shifts"] > 0 and da["window_shifts"] == db["window_shifts"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
