@@ -797,11 +797,12 @@ pf_status pf_checkpoint_save(pf_domain* d, const char* path) {
   };
   st = write_all();
   // the staging block covered the ghost planes of that copy: restore them
-  // whatever the outcome of the write
-  if (d->host.top_bc) {
-    PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
-    PF_HIP(hipStreamSynchronize(d->stream));
-  }
+  // whatever the outcome of the write; the copy no longer holds the chunks
+  // the bulk shortcut may take for equal in both copies: withdraw the flags
+  if (d->host.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
+  PF_HIP(hipMemsetAsync(reinterpret_cast<char*>(d->dev) + offsetof(DevDomain, pflag_ok), 0,
+                        sizeof(DevDomain::pflag_ok), d->stream));
+  PF_HIP(hipStreamSynchronize(d->stream));
   return st;
 }
 

@@ -325,6 +325,10 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
 // pure phase and every plane of the chunk marks that phase as a fixed point:
 // every face of every cell then has zero normal differences, so each cell
 // is a pure cell with A = 0, which the per-cell shortcut keeps exactly.
+// A copied chunk's flag also carries kSame: both field copies then hold its
+// phi, so when it is fixed again in the next step the copy is not needed.
+constexpr uint8_t kSame = 0x10;
+__device__ __forceinline__ int flag_phase(int f) { return f & 0x0F; }  // 0xFF -> 15: none
 
 // Tile and chunk coordinates of an item (uniform over the group; made
 // scalar so that the lookups below stay in scalar registers).
@@ -355,7 +359,7 @@ __device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, i
                                                 const TAB* tab) {
   if (!d.pflag_ok[d.cur_src]) return -1;
   const PF_CONST uint8_t* f = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src]));
-  const int a = f[chunk_index(d, c)];
+  const int a = flag_phase(f[chunk_index(d, c)]);
   if (a >= NP) return -1;
   for (int dz = -1; dz <= 1; ++dz) {
     const int jz = c.iz + dz;
@@ -368,7 +372,7 @@ __device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, i
       const int jy = c.iy + dy < 0 ? d.nty - 1 : (c.iy + dy == d.nty ? 0 : c.iy + dy);
       for (int dx = -1; dx <= 1; ++dx) {
         const int jx = c.ix + dx < 0 ? d.ntx - 1 : (c.ix + dx == d.ntx ? 0 : c.ix + dx);
-        if (f[(jz * d.nty + jy) * d.ntx + jx] != a) return -1;
+        if (flag_phase(f[(jz * d.nty + jy) * d.ntx + jx]) != a) return -1;
       }
     }
   }
@@ -666,7 +670,11 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
       if (t == 0) *to_global(X.jf) = 0u;
       continue;
     }
-    if (G.valid) {
+    // unless both copies already hold the chunk (copied or kept in the
+    // previous step too), copy it into the one this step writes
+    const bool same =
+        to_const(static_cast<const uint8_t*>(dd.pflag[dd.cur_src]))[chunk_index(dd, cid)] & kSame;
+    if (!same && G.valid) {
 #pragma unroll 4
       for (int k = G.z0; k < G.z1; ++k) {
         const V4<R> v = load4<R>(X.src, k, G.own_b);
@@ -675,7 +683,8 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
       }
     }
     if (t == 0) {
-      static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] = (uint8_t)fixed;
+      static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
+          (uint8_t)(fixed | kSame);
       dd_mark_flags(dd, X.dw);
       atomicAdd(X.jn + 1, 1u);
       uint32_t w = 0;

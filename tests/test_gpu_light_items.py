@@ -106,3 +106,29 @@ def test_bulk_flags_survive_variant_switches_and_window_shifts():
     log(f"switches: shifts {da['window_shifts']}, fixed items {da['fixed_items']}")
     assert da["window_shifts"] > 0 and da["window_shifts"] == db["window_shifts"]
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_bulk_skip_survives_a_checkpoint_save():
+    """A bulk chunk kept for two steps is not copied again (both field copies
+    hold it); saving a checkpoint uses the second copy as staging, so the
+    flags must be withdrawn: stepping on after a save equals the
+    shortcuts-off run bitwise."""
+    import os
+    import tempfile
+
+    shape = (96, 24, 70)
+    p = pfinputs.p0_params(solid_height=10)
+    p["dt"] = oracle.default_dt(p, shape)
+    out = {}
+    with tempfile.TemporaryDirectory() as tmp:
+        for sc in (0, 1):
+            q = dict(p, shortcuts=sc)
+            d = gpu_domain(shape, q, "fp64", 1, voronoi=(4, 7, 10))
+            d.step(6)
+            d.save_checkpoint(os.path.join(tmp, f"s{sc}.pfc"))
+            d.step(5)
+            out[sc] = (d.read(), d.diagnostics())
+            d.close()
+    (a, da), (b, _) = out[1], out[0]
+    assert da["fixed_items"] > 0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
