@@ -261,7 +261,7 @@ class Domain:
             "phi_max": dg.phi_max, "nonfinite": dg.nonfinite,
             "window_shifts": dg.window_shifts,
             "light_items": dg.light_items, "work_items": dg.work_items,
-            "fixed_items": dg.fixed_items,
+            "fixed_items": dg.fixed_items, "mu_pure_items": dg.mu_pure_items,
         }
 
 

@@ -65,7 +65,7 @@ class PfDiag(C.Structure):
         ("light_items", C.c_int32),
         ("work_items", C.c_int32),
         ("fixed_items", C.c_int32),
-        ("reserved", C.c_int32),
+        ("mu_pure_items", C.c_int32),
     ]
 
 

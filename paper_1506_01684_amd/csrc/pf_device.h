@@ -82,8 +82,15 @@ struct PlaneCoef {
   R chi1[NP][NM];       // chi_ai(T^{n+1}_k)
   R dchi[NP][NM];       // chi(T^{n+1}_k) - chi(T^n_k)  (difference in FP64)
   R dcbar[NP][NM];      // cbar(T^{n+1}_k) - cbar(T^n_k)
+  // for the mu-sweep of cells whose phi^n, phi^{n+1} and neighbours are all
+  // e_a, computed by the same functions as in the general face and cell
+  // stages (mu_face_m, mu_cell_h, mu_cell_chi), so bitwise the same values:
+  R cdl[NP][NM];        // cbar_ai - cbar_li, rounded as in mu_cell
+  R Mp[NP][NM];         // mu_face_m at pb = e_a, x/y faces
+  R MpZ[NP][NM];        // mu_face_m at pb = e_a, z face
+  R rchip[NP][NM];      // rcp_ of mu_cell's chi sum at phi^{n+1} = e_a
   int32_t pure_fixed;   // bit a: a pure-a cell with zero face terms maps to itself
-  int32_t pad;
+  int32_t chunk_fixed;  // first plane of a z chunk: pure_fixed of all its planes
 };
 
 // Device-resident descriptor of one domain.
@@ -108,7 +115,7 @@ struct DevDomain {
   double mu_fill[NM];         // mu of the liquid plane a shift adds / of the ghost plane
   void* copy[2];              // base of each 6-field copy
   void* coef;                 // PlaneCoef<R>[nz] of the running step
-  void* jfree;                // uint32 per work item of the tiled sweeps, then two counts
+  void* jfree;                // uint32 per work item of the tiled sweeps, then three counts
   int32_t nitems;             // work items of the tiled sweeps (index of those counts)
   int32_t pflag_ok[2];        // pflag[c] describes the state held in copy c
   void* pflag[2];             // uint8 per tile and z chunk [iz][iy][ix]: the phase all
@@ -357,19 +364,29 @@ __device__ __forceinline__ void phi_cell(const KP& P, const CP& C, const R ph[NP
 // mu_cell every rounding step is written out (fused where fma_ says so) and
 // contraction is off, so that each kernel evaluating these formulas rounds
 // them identically wherever they are inlined.
+template <typename R, bool ZF, typename CP>
+__device__ __forceinline__ void mu_face_m(const CP& C, const R pb[NP], R M[NM]) {
+#pragma clang fp contract(off)
+  M[0] = (R)(ZF ? C.DchiZ[0][0] : C.Dchi[0][0]) * pb[0];
+  M[1] = (R)(ZF ? C.DchiZ[0][1] : C.Dchi[0][1]) * pb[0];
+#pragma unroll
+  for (int a = 1; a < NP; ++a) {
+    M[0] = fma_(ZF ? C.DchiZ[a][0] : C.Dchi[a][0], pb[a], M[0]);
+    M[1] = fma_(ZF ? C.DchiZ[a][1] : C.Dchi[a][1], pb[a], M[1]);
+  }
+}
+template <typename R>
+__device__ __forceinline__ R mu_face_flux(R M, R mL, R mU, R inv_dx) {
+#pragma clang fp contract(off)
+  return M * (mU - mL) * inv_dx;
+}
 template <typename R, bool ZF, typename KP, typename CP>
 __device__ __forceinline__ void mu_face_diff(const KP& P, const CP& C, const R pb[NP],
                                              const R mL[NM], const R mU[NM], R Phi[NM]) {
-#pragma clang fp contract(off)
-  R M0 = (R)(ZF ? C.DchiZ[0][0] : C.Dchi[0][0]) * pb[0];
-  R M1 = (R)(ZF ? C.DchiZ[0][1] : C.Dchi[0][1]) * pb[0];
-#pragma unroll
-  for (int a = 1; a < NP; ++a) {
-    M0 = fma_(ZF ? C.DchiZ[a][0] : C.Dchi[a][0], pb[a], M0);
-    M1 = fma_(ZF ? C.DchiZ[a][1] : C.Dchi[a][1], pb[a], M1);
-  }
-  Phi[0] = M0 * (mU[0] - mL[0]) * (R)P.inv_dx;
-  Phi[1] = M1 * (mU[1] - mL[1]) * (R)P.inv_dx;
+  R M[NM];
+  mu_face_m<R, ZF>(C, pb, M);
+  Phi[0] = mu_face_flux<R>(M[0], mL[0], mU[0], (R)P.inv_dx);
+  Phi[1] = mu_face_flux<R>(M[1], mL[1], mU[1], (R)P.inv_dx);
 }
 
 // The anti-trapping current vanishes exactly unless some solid phase and the
@@ -426,36 +443,70 @@ __device__ __forceinline__ void mu_face(const KP& P, const CP& C, const R pb[NP]
 //   src_i = sum_a (h1_a - h0_a)(chi_ai mu_i + cbar_ai - cbar_li)
 //         + sum_a h1_a (dchi_ai mu_i + dcbar_ai)
 //   mu_i^{n+1} = mu_i + (dt div_i - src_i) / sum_a h1_a chi_ai(T^{n+1})
+// h_a = phi_a^2 / sum_b phi_b^2 of one cell.
+template <typename R>
+__device__ __forceinline__ void mu_cell_h(const R p[NP], R h[NP]) {
+#pragma clang fp contract(off)
+  R S = p[0] * p[0];
+#pragma unroll
+  for (int a = 1; a < NP; ++a) S = fma_(p[a], p[a], S);
+  const R i = rcp_(S);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) h[a] = p[a] * p[a] * i;
+}
+// src_i for component q; dh = h1 - h0, cd_a = cbar_ai - cbar_li.
+template <typename R, typename CP>
+__device__ __forceinline__ R mu_cell_src(const CP& C, int q, const R dh[NP], const R h1[NP], R mu,
+                                         const R cd[NP]) {
+#pragma clang fp contract(off)
+  R src = R(0);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    const R ca = fma_(C.chi[a][q], mu, cd[a]);
+    const R ta = fma_(C.dchi[a][q], mu, C.dcbar[a][q]);
+    src = fma_(dh[a], ca, src);
+    src = fma_(h1[a], ta, src);
+  }
+  return src;
+}
+// src of a cell with phi^n = phi^{n+1} = e_a (h_a = ha = 1, h1 - h0 = +0):
+// the one term of the sum above that is not a finite value times +0.
+template <typename R>
+__device__ __forceinline__ R mu_pure_src(R ha, R dchi_a, R dcbar_a, R mu) {
+#pragma clang fp contract(off)
+  return fma_(ha, fma_(dchi_a, mu, dcbar_a), R(0));
+}
+// sum_a h1_a chi_ai(T^{n+1}) for component q.
+template <typename R, typename CP>
+__device__ __forceinline__ R mu_cell_chi(const CP& C, int q, const R h1[NP]) {
+#pragma clang fp contract(off)
+  R chi = R(0);
+#pragma unroll
+  for (int a = 0; a < NP; ++a) chi = fma_(h1[a], C.chi1[a][q], chi);
+  return chi;
+}
+template <typename R, typename KP>
+__device__ __forceinline__ R mu_cell_out(const KP& P, R div, R src, R rchi, R mu) {
+#pragma clang fp contract(off)
+  return fma_(fma_(P.dt, div, -src), rchi, mu);
+}
 template <typename R, typename KP, typename CP>
 __device__ __forceinline__ void mu_cell(const KP& P, const CP& C, const R p0[NP], const R p1[NP],
                                         const R mu[NM], const R div[NM], R out[NM]) {
 #pragma clang fp contract(off)
-  R S0 = p0[0] * p0[0], S1 = p1[0] * p1[0];
+  R h0[NP], h1[NP], dh[NP];
+  mu_cell_h<R>(p0, h0);
+  mu_cell_h<R>(p1, h1);
 #pragma unroll
-  for (int a = 1; a < NP; ++a) {
-    S0 = fma_(p0[a], p0[a], S0);
-    S1 = fma_(p1[a], p1[a], S1);
-  }
-  const R i0 = rcp_(S0), i1 = rcp_(S1);
-  R h0[NP], h1[NP];
-#pragma unroll
-  for (int a = 0; a < NP; ++a) {
-    h0[a] = p0[a] * p0[a] * i0;
-    h1[a] = p1[a] * p1[a] * i1;
-  }
+  for (int a = 0; a < NP; ++a) dh[a] = h1[a] - h0[a];
 #pragma unroll
   for (int q = 0; q < NM; ++q) {
     const R cref = (R)C.cbar[LQ][q];
-    R src = R(0), chi = R(0);
+    R cd[NP];
 #pragma unroll
-    for (int a = 0; a < NP; ++a) {
-      const R ca = fma_(C.chi[a][q], mu[q], (R)C.cbar[a][q] - cref);
-      const R ta = fma_(C.dchi[a][q], mu[q], C.dcbar[a][q]);
-      src = fma_(h1[a] - h0[a], ca, src);
-      src = fma_(h1[a], ta, src);
-      chi = fma_(h1[a], C.chi1[a][q], chi);
-    }
-    out[q] = fma_(fma_(P.dt, div[q], -src), rcp_(chi), mu[q]);
+    for (int a = 0; a < NP; ++a) cd[a] = (R)C.cbar[a][q] - cref;
+    const R src = mu_cell_src<R>(C, q, dh, h1, mu[q], cd);
+    out[q] = mu_cell_out<R>(P, div[q], src, rcp_(mu_cell_chi<R>(C, q, h1)), mu[q]);
   }
 }
 

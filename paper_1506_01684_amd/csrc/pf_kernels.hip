@@ -45,10 +45,12 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     return;
   }
   // counts of this step's items that the phi-sweep finds free of
-  // anti-trapping faces, and that it copies unchanged
+  // anti-trapping faces, that it copies unchanged, and that the mu-sweep
+  // evaluates from mu alone
   if (threadIdx.x == 0) {
     static_cast<uint32_t*>(d.jfree)[d.nitems] = 0u;
     static_cast<uint32_t*>(d.jfree)[d.nitems + 1] = 0u;
+    static_cast<uint32_t*>(d.jfree)[d.nitems + 2] = 0u;
   }
   // Moving window: has the front passed plane window_z?  The liquid
   // fraction of that plane of the current state is summed in FP64 (strided
@@ -125,6 +127,16 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m), m the mean.  The
     // projection returns e_a exactly when every y_b stays below
     // y_a - 1 = rate_a m; the margin covers FP32 rounding of y.
+    // coefficients of the mu-sweep of pure items (mu_pure_body)
+    for (int a = 0; a < NP; ++a) {
+      for (int q = 0; q < NM; ++q) c.cdl[a][q] = c.cbar[a][q] - c.cbar[LQ][q];
+      R e[NP], h[NP];
+      for (int b = 0; b < NP; ++b) e[b] = b == a ? R(1) : R(0);
+      mu_cell_h<R>(e, h);
+      mu_face_m<R, false>(c, e, c.Mp[a]);
+      mu_face_m<R, true>(c, e, c.MpZ[a]);
+      for (int q = 0; q < NM; ++q) c.rchip[a][q] = rcp_(mu_cell_chi<R>(c, q, h));
+    }
     c.pure_fixed = 0;
     for (int a = 0; a < NP; ++a) {
       double rhs[NP], m = 0.0;
@@ -142,8 +154,15 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
       }
       if (fixed) c.pure_fixed |= 1 << a;
     }
-    c.pad = 0;
+    c.chunk_fixed = 0;
     tab[k] = c;
+  }
+  __syncthreads();
+  // the fixed points of every plane of each z chunk, at its first plane
+  for (int iz = threadIdx.x; iz < d.nzc; iz += blockDim.x) {
+    int m = ~0;
+    for (int k = iz * d.zc; k < d.nz && k < (iz + 1) * d.zc; ++k) m &= tab[k].pure_fixed;
+    tab[iz * d.zc].chunk_fixed = m;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -21,6 +21,8 @@ struct LaunchSet {
 
 // Threads per work group of the sweeps (tile tx * ty).
 constexpr int kTileThreads = 256;
+// Most z planes per work item of the tiled sweeps.
+constexpr int kMaxZc = 32;
 
 hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s);
 hipError_t launch_window(const LaunchSet& L, int prec, hipStream_t s);

@@ -67,7 +67,7 @@ Tiling choose_tiling(int nx, int ny, int nz) {
   // so the halo cells one tile loads are evicted from L2 before its
   // neighbour reads them; short ones re-load more ring planes.
   const int64_t cols = (int64_t)nz * t.ntx * t.nty;
-  const int64_t zc = std::min<int64_t>(32, std::max<int64_t>(8, cols / 2048));
+  const int64_t zc = std::min<int64_t>(kMaxZc, std::max<int64_t>(8, cols / 2048));
   t.zc = (int32_t)std::min<int64_t>(zc, nz);
   t.nzc = (nz + t.zc - 1) / t.zc;
   // y-slab order when it leaves at most 1/8 of the blocks without a tile
@@ -120,8 +120,8 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
   off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
   const Tiling T = choose_tiling(d.nx, d.ny, d.nz);
-  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and two counts
-  off = align_up(off + sizeof(uint32_t) * ((size_t)T.blocks() + 2), kAlign);
+  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and three counts
+  off = align_up(off + sizeof(uint32_t) * ((size_t)T.blocks() + 3), kAlign);
   L.pflag_bytes = align_up((size_t)T.ntx * T.nty * T.nzc, kAlign);
   L.off_pflag = off;  // the pure-phase flags of each copy's state
   off += 2 * L.pflag_bytes;
@@ -539,7 +539,7 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   if ((st = upload_desc(d)) != PF_OK) return st;
   // no step has classified the items yet
   PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
-                        2 * sizeof(uint32_t), d->stream));
+                        3 * sizeof(uint32_t), d->stream));
   if (in->kind == PF_INIT_VORONOI) {
     if (in->nseeds < 0 || in->solid_height < 0)
       return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
@@ -711,11 +711,12 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->phi_max = v[8];
     diag->nonfinite = (int64_t)v[9];
     diag->window_shifts = cur.shifts;
-    uint32_t counts[2] = {0, 0};
+    uint32_t counts[3] = {0, 0, 0};
     PF_HIP(hipMemcpy(counts, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(),
                      sizeof(counts), hipMemcpyDeviceToHost));
     diag->light_items = (int32_t)counts[0];
     diag->fixed_items = (int32_t)counts[1];
+    diag->mu_pure_items = (int32_t)counts[2];
     diag->work_items = d->T.blocks();
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
@@ -846,7 +847,7 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path) {
   hd.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
   PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
-                        2 * sizeof(uint32_t), d->stream));
+                        3 * sizeof(uint32_t), d->stream));
   PF_HIP(launch_ckpt_unpack(d->dev, g.prec, cells, 0, stage, d->stream));
   if (hd.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
   PF_HIP(hipStreamSynchronize(d->stream));

@@ -353,32 +353,64 @@ __device__ __forceinline__ void dd_mark_flags(const DD& d, DevDomain* dw) {
   to_global(&dw->pflag_ok[d.cur_src ^ 1])[0] = 1;
 }
 
-// The phase of a bulk chunk that may be copied, or -1 (uniform over the group).
+// Flag bytes of a chunk's 27-chunk neighbourhood (periodic in x and y; a z
+// neighbour outside the domain reads the chunk itself), all loaded before
+// any is tested, so that the loads overlap instead of taking one round trip
+// each.
+template <typename DD>
+__device__ __forceinline__ void neighbour_flags(const DD& d, const PF_CONST uint8_t* f,
+                                                const ChunkId& c, int v[27]) {
+  int jx[3], jy[3], jz[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int x = c.ix + i - 1, y = c.iy + i - 1, z = c.iz + i - 1;
+    jx[i] = x < 0 ? d.ntx - 1 : (x == d.ntx ? 0 : x);
+    jy[i] = y < 0 ? d.nty - 1 : (y == d.nty ? 0 : y);
+    jz[i] = z < 0 || z >= d.nzc ? c.iz : z;
+  }
+#pragma unroll
+  for (int i = 0; i < 27; ++i) v[i] = f[(jz[i / 9] * d.nty + jy[(i / 3) % 3]) * d.ntx + jx[i % 3]];
+}
+
+// The phase of a bulk chunk that may be copied, or -1 (uniform over the
+// group): the chunk and its 26 neighbours hold phase a purely (at the z ends
+// the mirror adds nothing; the ghost plane of a Dirichlet top is liquid),
+// and every plane of the chunk marks a as a fixed point.
 template <typename DD, typename TAB>
-__device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, int z0, int z1,
+__device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, int z0,
                                                 const TAB* tab) {
   if (!d.pflag_ok[d.cur_src]) return -1;
   const PF_CONST uint8_t* f = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src]));
   const int a = flag_phase(f[chunk_index(d, c)]);
   if (a >= NP) return -1;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int jz = c.iz + dz;
-    if (jz < 0) continue;  // mirror: the chunk's own bottom plane
-    if (jz >= d.nzc) {     // mirror, or the liquid ghost plane of a Dirichlet top
-      if (d.top_bc && a != LQ) return -1;
-      continue;
-    }
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int jy = c.iy + dy < 0 ? d.nty - 1 : (c.iy + dy == d.nty ? 0 : c.iy + dy);
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int jx = c.ix + dx < 0 ? d.ntx - 1 : (c.ix + dx == d.ntx ? 0 : c.ix + dx);
-        if (flag_phase(f[(jz * d.nty + jy) * d.ntx + jx]) != a) return -1;
-      }
-    }
-  }
-  for (int k = z0; k < z1; ++k)
-    if (!((tab[k].pure_fixed >> a) & 1)) return -1;
-  return a;
+  if (c.iz + 1 >= d.nzc && d.top_bc && a != LQ) return -1;
+  int v[27];
+  neighbour_flags(d, f, c, v);
+  bool ok = ((tab[z0].chunk_fixed >> a) & 1) != 0;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) ok = ok && flag_phase(v[i]) == a;
+  return ok ? a : -1;
+}
+
+// The phase a when this step's phi_bulk_kernel kept the item's chunk and
+// all 26 neighbouring chunks in phase a (their flags in the copy being
+// written read a | kSame; the sweep itself never writes kSame), else -1.
+// Then phi^n = phi^{n+1} = e_a on every cell the mu-sweep reads for the
+// item: the chunks are pure in phi^n and copied unchanged, and the cells
+// read lie at most one cell outside the chunk.  Uniform over the group.
+template <typename DD>
+__device__ __forceinline__ int mu_pure_phase(const DD& d, const ChunkId& c) {
+  const PF_CONST uint8_t* f = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src ^ 1]));
+  const int own = f[chunk_index(d, c)];
+  const int a = flag_phase(own);
+  if (a >= NP || own != (a | kSame)) return -1;
+  if (c.iz + 1 >= d.nzc && d.top_bc && a != LQ) return -1;
+  int v[27];
+  neighbour_flags(d, f, c, v);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) ok = ok && v[i] == own;
+  return ok ? a : -1;
 }
 
 // The phase a cell holds purely (phi = e_a exactly), or -1.
@@ -431,7 +463,6 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
     const int kstart = G.z0 - 1;
     const PF_CONST DevDomain& dd = *X.dp;
     const ChunkId cid = chunk_id(dd, G);
-    const int z0 = __builtin_amdgcn_readfirstlane(G.z0), z1 = __builtin_amdgcn_readfirstlane(G.z1);
 
     // chunks copied unchanged by phi_bulk_kernel (launched just before)
     if (*to_const(X.jf) & kBulkDone) continue;
@@ -664,8 +695,8 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
     const auto& P = kparams<R>(*X.dp);
     const PF_CONST DevDomain& dd = *X.dp;
     const ChunkId cid = chunk_id(dd, G);
-    const int z0 = __builtin_amdgcn_readfirstlane(G.z0), z1 = __builtin_amdgcn_readfirstlane(G.z1);
-    const int fixed = P.shortcuts ? bulk_fixed_phase(dd, cid, z0, z1, X.tab) : -1;
+    const int z0 = __builtin_amdgcn_readfirstlane(G.z0);
+    const int fixed = P.shortcuts ? bulk_fixed_phase(dd, cid, z0, X.tab) : -1;
     if (fixed < 0) {
       if (t == 0) *to_global(X.jf) = 0u;
       continue;
@@ -746,6 +777,8 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
         }
       continue;
     }
+    // items pure in one phase: mu_pure_kernel
+    if (P.shortcuts && mu_pure_phase(*X.dp, chunk_id(*X.dp, G)) >= 0) continue;
 
     // lane l of the edge wave takes the lower-edge face of tile row l (x)
     // or tile column l (y), between x0-1 and x0 / y0-1 and y0
@@ -1038,6 +1071,8 @@ __device__ __forceinline__ void mu_bulk_body(DevDomain* const* doms, const int32
     const Copy& src = X.src;  // phi^n (fields 0-3), mu^n (4-5)
     const Copy& dst = X.dst;  // phi^{n+1}, mu^{n+1}
     const R inv_dx = (R)P.inv_dx;
+    // items pure in one phase: mu_pure_kernel
+    if (P.shortcuts && mu_pure_phase(*X.dp, chunk_id(*X.dp, G)) >= 0) continue;
     const bool ex_ok = lane < G.ty && G.y0 + lane < g.ny;
     const bool ey_ok = lane < G.tx && G.x0 + lane < g.nx;
     const int kstart = G.z0 - 1;
@@ -1152,6 +1187,151 @@ __global__ __launch_bounds__(kTileThreads) void mu_bulk_f64(DevDomain* const* do
   mu_bulk_body<double>(doms, first, ndom, total);
 }
 
+
+// The coefficients of one plane that a cell pure in phase a uses, in the
+// order mu_pure_body stages them, two components each: Mp, MpZ, rchip, and
+// dchi, dcbar of phase a.
+constexpr int kPureCoef = 5 * NM;
+template <typename R>
+__device__ __forceinline__ R pure_coef(const PF_CONST PlaneCoef<R>& C, int a, int j) {
+  const int q = j & 1;
+  switch (j >> 1) {
+    case 0: return C.Mp[a][q];
+    case 1: return C.MpZ[a][q];
+    case 2: return C.rchip[a][q];
+    case 3: return C.dchi[a][q];
+    default: return C.dcbar[a][q];
+  }
+}
+
+// mu-sweep of the items that mu_pure_phase finds pure in phase a: phi^n =
+// phi^{n+1} = e_a on every cell read, so a thread needs only mu^n of its
+// column and of its four lateral neighbours.  No barriers inside an item:
+// the waves run independently, and the few registers let many of them
+// share a SIMD to cover the load latency.
+//
+// Same result as the other bodies, operation by operation: each face flux
+// is mu_face_flux of the same two mu values with the coefficient M that
+// mu_face_m gives at pb = e_a (the plane's Mp, MpZ, computed by that
+// function); the divergence sums the fluxes in the same order; in mu_cell
+// at phi^n = phi^{n+1} = e_a, h = e_a exactly and h1 - h0 = +0, so every
+// term of the src sum but one multiplies a finite value by +0 and adds a
+// zero: src is fma_(h_a, ta_a, +0), which is what the full sum gives (a
+// zero sum stays +0 before and after that term); the chi sum's reciprocal
+// is the plane's rchip.  For every finite state mu^{n+1} is bitwise the
+// other bodies', from a third of the bytes and a quarter of the arithmetic.
+template <typename R>
+__device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32_t* first, int ndom,
+                                             int total) {
+  // the item's plane coefficients, staged once (the table is too large for
+  // the scalar cache, and a scalar load per value and plane would put a
+  // round trip to L2 into every plane)
+  __shared__ R s_cf[kMaxZc][kPureCoef];
+  const int t = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    ItemCtx<R> X;
+    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    const auto& P = kparams<R>(*X.dp);
+    if (!P.shortcuts || P.mu_frozen) continue;  // uniform
+    const int a = mu_pure_phase(*X.dp, chunk_id(*X.dp, X.G));
+    if (a < 0) continue;  // uniform
+    if (t == 0) atomicAdd(X.jn + 2, 1u);
+    const TileGeo& G = X.G;
+    __syncthreads();  // the previous item's coefficients are consumed
+    for (int i = t; i < (G.z1 - G.z0) * kPureCoef; i += blockDim.x)
+      s_cf[i / kPureCoef][i % kPureCoef] = pure_coef<R>(X.tab[G.z0 + i / kPureCoef], a, i % kPureCoef);
+    __syncthreads();
+    if (!G.valid) continue;  // no barriers below
+    const Geo& g = X.g;
+    const Copy& src = X.src;
+    const Copy& dst = X.dst;
+    const R inv_dx = (R)P.inv_dx;
+    R ha;  // h_a of a cell holding e_a (1)
+    {
+      R e[NP], h[NP];
+#pragma unroll
+      for (int b = 0; b < NP; ++b) e[b] = b == a ? R(1) : R(0);
+      mu_cell_h<R>(e, h);
+      ha = h[a];
+    }
+    const int gx = G.x0 + G.lx, gy = G.y0 + G.ly;
+    const uint32_t row = (uint32_t)gy * (uint32_t)g.pitch, rs = sizeof(R);
+    // lateral neighbours: x-1, x+1, y-1, y+1 (periodic)
+    const uint32_t nb[4] = {(row + g.xm(gx)) * rs, (row + g.xp(gx)) * rs,
+                            ((uint32_t)g.ym(gy) * g.pitch + gx) * rs,
+                            ((uint32_t)g.yp(gy) * g.pitch + gx) * rs};
+    // the z face below z0 as the sweep of the plane below evaluates it
+    const int kb = G.z0 - 1;
+    R m[NM] = {ldg<R>(src.at(4, G.z0), G.own_b), ldg<R>(src.at(5, G.z0), G.own_b)};
+    R Pzl[NM] = {R(0), R(0)};
+    if (g.zface(kb)) {
+      const R mb[NM] = {ldg<R>(src.at(4, g.zc(kb)), G.own_b), ldg<R>(src.at(5, g.zc(kb)), G.own_b)};
+#pragma unroll
+      for (int q = 0; q < NM; ++q) Pzl[q] = mu_face_flux<R>(X.tab[kb].MpZ[a][q], mb[q], m[q], inv_dx);
+    }
+    // Loads of plane k: mu^n of the own column above it and of the lateral
+    // neighbours.  Two buffers alternate so that the loads of plane k+1 are
+    // issued before plane k is evaluated and stored, and no value in flight
+    // is copied between registers (which would wait for it, and for the
+    // stores issued before it, at once).
+    struct Buf {
+      R up[NM];
+      R L[4][NM];
+    };
+    const auto issue = [&](int k, Buf& b) {
+      const int k1 = g.zp(k);
+      b.up[0] = ldg<R>(src.at(4, k1), G.own_b);
+      b.up[1] = ldg<R>(src.at(5, k1), G.own_b);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        b.L[n][0] = ldg<R>(src.at(4, k), nb[n]);
+        b.L[n][1] = ldg<R>(src.at(5, k), nb[n]);
+      }
+    };
+    const auto plane = [&](int k, const Buf& b) {
+      const R* cf = s_cf[k - G.z0];
+      const bool zf = g.zface(k);
+#pragma unroll
+      for (int q = 0; q < NM; ++q) {
+        const R Mxy = cf[q];
+        const R fxl = mu_face_flux<R>(Mxy, b.L[0][q], m[q], inv_dx);
+        const R fxu = mu_face_flux<R>(Mxy, m[q], b.L[1][q], inv_dx);
+        const R fyl = mu_face_flux<R>(Mxy, b.L[2][q], m[q], inv_dx);
+        const R fyu = mu_face_flux<R>(Mxy, m[q], b.L[3][q], inv_dx);
+        const R Pzu = zf ? mu_face_flux<R>(cf[2 + q], m[q], b.up[q], inv_dx) : R(0);
+        R div = R(0);
+        div += fxu - fxl;
+        div += fyu - fyl;
+        div = (div + (Pzu - Pzl[q])) * inv_dx;
+        Pzl[q] = Pzu;
+        const R sq = mu_pure_src<R>(ha, cf[6 + q], cf[8 + q], m[q]);
+        stg<R>(dst.at(4 + q, k), G.own_b, mu_cell_out<R>(P, div, sq, cf[4 + q], m[q]));
+      }
+      m[0] = b.up[0];
+      m[1] = b.up[1];
+    };
+    Buf A, B;
+    issue(G.z0, A);
+    for (int k = G.z0; k < G.z1; k += 2) {
+      if (k + 1 < G.z1) issue(k + 1, B);
+      plane(k, A);
+      if (k + 1 < G.z1) {
+        if (k + 2 < G.z1) issue(k + 2, A);
+        plane(k + 1, B);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void mu_pure_f64(DevDomain* const* doms, const int32_t* first,
+                                                            int ndom, int total) {
+  mu_pure_body<double>(doms, first, ndom, total);
+}
+__global__ __launch_bounds__(kTileThreads) void mu_pure_f32(DevDomain* const* doms, const int32_t* first,
+                                                            int ndom, int total) {
+  mu_pure_body<float>(doms, first, ndom, total);
+}
+
 // --------------------------------------------------------------- launches
 
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
@@ -1174,16 +1354,19 @@ hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_
   return hipGetLastError();
 }
 
-// The FP64 mu-sweep is two launches over the same items: mu_tiled_f64
-// takes the items whose faces may carry the anti-trapping current,
-// mu_bulk_f64 the rest (all items go to mu_tiled_f64 in a step with few
-// light ones).  The FP32 sweep is one launch.
+// The mu-sweep launches over the same items: mu_pure_* takes the items pure
+// in one phase; in FP64 mu_tiled_f64 takes the items whose faces may carry
+// the anti-trapping current, mu_bulk_f64 the rest (all of them go to
+// mu_tiled_f64 in a step with few light ones); in FP32 mu_tiled_f32 takes
+// every other item.
 hipError_t launch_mu_tiled(const LaunchSet& L, int prec, hipStream_t s) {
   const int grid = L.total;
   if (prec == 0) {
+    mu_pure_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     mu_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     mu_bulk_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   } else {
+    mu_pure_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     mu_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   }
   return hipGetLastError();

@@ -24,11 +24,14 @@ def _run(shape, p, prec, steps, shortcuts, voronoi, variant=1):
     return out, dg
 
 
-@pytest.mark.parametrize("hs,aniso", [(4, False), (4, True), (40, False)])
+@pytest.mark.parametrize("hs,aniso", [(4, False), (4, True), (40, False), (24, False)])
 def test_split_is_bitwise_exact(hs, aniso):
-    """Mostly liquid (hs = 4): most items are light and the split runs;
+    """Mostly liquid (hs = 4): most items are light and the split runs, and
+    the top chunks take the mu-from-mu-alone path inside the light kernel;
     mostly solid (hs = 40 of 64): liquid films along the lamella boundaries
-    make most items heavy.  Either way shortcuts on equals shortcuts off."""
+    make most items heavy; half liquid (hs = 24): too few light items for
+    the split, so the full kernel takes the pure top chunks too.  Either way
+    shortcuts on equals shortcuts off."""
     shape = (64, 40, 70)
     p = pfinputs.p0_params(solid_height=hs, delta_sl=0.05 if aniso else 0.0)
     p["dt"] = oracle.default_dt(p, shape)
@@ -36,10 +39,14 @@ def test_split_is_bitwise_exact(hs, aniso):
     b, db = _run(shape, p, "fp64", 12, 0, (5, 9, hs))
     frac = da["light_items"] / da["work_items"]
     log(f"split hs={hs} aniso={aniso}: light items {da['light_items']} of {da['work_items']} "
-        f"({frac:.2f}), max |dmu| {np.max(np.abs(a[1] - b[1])):.1e}")
-    assert db["light_items"] == 0
+        f"({frac:.2f}), mu from mu alone {da['mu_pure_items']}, "
+        f"max |dmu| {np.max(np.abs(a[1] - b[1])):.1e}")
+    assert db["light_items"] == 0 and db["mu_pure_items"] == 0
     if hs == 4:
         assert frac >= 0.6  # the light kernel really ran
+        assert da["mu_pure_items"] > 0
+    if hs == 24:
+        assert frac < 0.6 and da["mu_pure_items"] > 0
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
@@ -67,8 +74,10 @@ def test_light_items_reported_only_for_the_fp64_tiled_sweep():
 def test_bulk_chunks_are_copied_exactly(prec, aniso, top_bc):
     """Chunks that hold one pure phase, with all their neighbours, at a fixed
     point are copied by the phi bulk shortcut: most of a tall liquid column
-    is; the result equals the shortcuts-off run bitwise (with the Dirichlet
-    top too, whose liquid ghost allows only liquid chunks at the top)."""
+    is; the mu-sweep of a kept chunk whose neighbours were all kept reads mu
+    alone.  The result equals the shortcuts-off run bitwise (with the
+    Dirichlet top too, whose liquid ghost allows only liquid chunks at the
+    top)."""
     shape = (96, 24, 70)
     p = pfinputs.p0_params(solid_height=10, delta_sl=0.05 if aniso else 0.0)
     p["top_bc"] = top_bc
@@ -76,8 +85,10 @@ def test_bulk_chunks_are_copied_exactly(prec, aniso, top_bc):
     a, da = _run(shape, p, prec, 10, 1, (4, 7, 10))
     b, db = _run(shape, p, prec, 10, 0, (4, 7, 10))
     log(f"bulk {prec} aniso={aniso} top_bc={top_bc}: fixed items {da['fixed_items']} of "
-        f"{da['work_items']}")
+        f"{da['work_items']}, mu from mu alone {da['mu_pure_items']}")
     assert da["fixed_items"] > da["work_items"] // 3 and db["fixed_items"] == 0
+    # the chunks kept with all their neighbours: mu from mu alone
+    assert 0 < da["mu_pure_items"] <= da["fixed_items"] and db["mu_pure_items"] == 0
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
@@ -130,5 +141,5 @@ def test_bulk_skip_survives_a_checkpoint_save():
             out[sc] = (d.read(), d.diagnostics())
             d.close()
     (a, da), (b, _) = out[1], out[0]
-    assert da["fixed_items"] > 0
+    assert da["fixed_items"] > 0 and da["mu_pure_items"] > 0
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
