@@ -39,6 +39,21 @@ constexpr int LQ = 3;   // liquid index
 constexpr int NPAIR = 6;
 constexpr int NFIELD = 6;  // phi_0..phi_3, mu_0, mu_1 in one copy
 
+// Per-step counts of the tiled sweeps, after the item words of jfree: the
+// light items (no anti-trapping face), the items the phi bulk shortcut
+// keeps, and the items whose mu-sweep reads mu alone.  Increments of one
+// address are serialised, so each count is spread over kCountSlots words
+// on 128-byte lines of their own (the work item's number picks the slot).
+constexpr int kCountKinds = 3, kCountSlots = 8, kCountStride = 32;  // stride in words
+constexpr int kCountLight = 0, kCountFixed = 1, kCountPure = 2;
+constexpr int kCountWords = kCountKinds * kCountSlots * kCountStride;
+__host__ __device__ inline int64_t count_base(int64_t nitems) {  // word offset in jfree
+  return (nitems + kCountStride - 1) / kCountStride * kCountStride;
+}
+__host__ __device__ inline int64_t count_word(int kind, int slot) {
+  return (int64_t)(kind * kCountSlots + slot) * kCountStride;
+}
+
 // pair index of (a,b), a < b: (0,1)=0 (0,2)=1 (0,3)=2 (1,2)=3 (1,3)=4 (2,3)=5
 __host__ __device__ constexpr int pair_index(int a, int b) {
   return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
@@ -115,7 +130,7 @@ struct DevDomain {
   double mu_fill[NM];         // mu of the liquid plane a shift adds / of the ghost plane
   void* copy[2];              // base of each 6-field copy
   void* coef;                 // PlaneCoef<R>[nz] of the running step
-  void* jfree;                // uint32 per work item of the tiled sweeps, then three counts
+  void* jfree;                // uint32 per work item of the tiled sweeps, then the counts
   int32_t nitems;             // work items of the tiled sweeps (index of those counts)
   int32_t pflag_ok[2];        // pflag[c] describes the state held in copy c
   void* pflag[2];             // uint8 per tile and z chunk [iz][iy][ix]: the phase all

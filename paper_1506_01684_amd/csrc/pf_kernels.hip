@@ -47,11 +47,9 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
   // counts of this step's items that the phi-sweep finds free of
   // anti-trapping faces, that it copies unchanged, and that the mu-sweep
   // evaluates from mu alone
-  if (threadIdx.x == 0) {
-    static_cast<uint32_t*>(d.jfree)[d.nitems] = 0u;
-    static_cast<uint32_t*>(d.jfree)[d.nitems + 1] = 0u;
-    static_cast<uint32_t*>(d.jfree)[d.nitems + 2] = 0u;
-  }
+  if (threadIdx.x < kCountKinds * kCountSlots)
+    static_cast<uint32_t*>(d.jfree)[count_base(d.nitems) +
+                                    count_word(threadIdx.x / kCountSlots, threadIdx.x % kCountSlots)] = 0u;
   // Moving window: has the front passed plane window_z?  The liquid
   // fraction of that plane of the current state is summed in FP64 (strided
   // per thread, then a fixed tree); below half the plane area the step
@@ -154,16 +152,13 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
       }
       if (fixed) c.pure_fixed |= 1 << a;
     }
-    c.chunk_fixed = 0;
+    c.chunk_fixed = ~0;
     tab[k] = c;
   }
   __syncthreads();
   // the fixed points of every plane of each z chunk, at its first plane
-  for (int iz = threadIdx.x; iz < d.nzc; iz += blockDim.x) {
-    int m = ~0;
-    for (int k = iz * d.zc; k < d.nz && k < (iz + 1) * d.zc; ++k) m &= tab[k].pure_fixed;
-    tab[iz * d.zc].chunk_fixed = m;
-  }
+  for (int k = threadIdx.x; k < d.nz; k += blockDim.x)
+    atomicAnd(&tab[k / d.zc * d.zc].chunk_fixed, tab[k].pure_fixed);
   __syncthreads();
   if (threadIdx.x == 0) {
     // the pure-phase flags of the copy this step writes are renewed by the

@@ -120,8 +120,8 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
   off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
   const Tiling T = choose_tiling(d.nx, d.ny, d.nz);
-  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, and three counts
-  off = align_up(off + sizeof(uint32_t) * ((size_t)T.blocks() + 3), kAlign);
+  L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, then the counts
+  off = align_up(off + sizeof(uint32_t) * ((size_t)count_base(T.blocks()) + kCountWords), kAlign);
   L.pflag_bytes = align_up((size_t)T.ntx * T.nty * T.nzc, kAlign);
   L.off_pflag = off;  // the pure-phase flags of each copy's state
   off += 2 * L.pflag_bytes;
@@ -538,8 +538,8 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   h.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
   // no step has classified the items yet
-  PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
-                        3 * sizeof(uint32_t), d->stream));
+  PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)count_base(d->T.blocks()),
+                        0, sizeof(uint32_t) * kCountWords, d->stream));
   if (in->kind == PF_INIT_VORONOI) {
     if (in->nseeds < 0 || in->solid_height < 0)
       return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
@@ -711,12 +711,15 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->phi_max = v[8];
     diag->nonfinite = (int64_t)v[9];
     diag->window_shifts = cur.shifts;
-    uint32_t counts[3] = {0, 0, 0};
-    PF_HIP(hipMemcpy(counts, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(),
-                     sizeof(counts), hipMemcpyDeviceToHost));
-    diag->light_items = (int32_t)counts[0];
-    diag->fixed_items = (int32_t)counts[1];
-    diag->mu_pure_items = (int32_t)counts[2];
+    uint32_t words[kCountWords];
+    PF_HIP(hipMemcpy(words, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)count_base(d->T.blocks()),
+                     sizeof(words), hipMemcpyDeviceToHost));
+    uint32_t counts[kCountKinds] = {};
+    for (int k = 0; k < kCountKinds; ++k)
+      for (int sl = 0; sl < kCountSlots; ++sl) counts[k] += words[count_word(k, sl)];
+    diag->light_items = (int32_t)counts[kCountLight];
+    diag->fixed_items = (int32_t)counts[kCountFixed];
+    diag->mu_pure_items = (int32_t)counts[kCountPure];
     diag->work_items = d->T.blocks();
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
@@ -846,8 +849,8 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path) {
   hd.shift_now = 0;
   hd.steps_left = -1;
   if ((st = upload_desc(d)) != PF_OK) return st;
-  PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)d->T.blocks(), 0,
-                        3 * sizeof(uint32_t), d->stream));
+  PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)count_base(d->T.blocks()),
+                        0, sizeof(uint32_t) * kCountWords, d->stream));
   PF_HIP(launch_ckpt_unpack(d->dev, g.prec, cells, 0, stage, d->stream));
   if (hd.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
   PF_HIP(hipStreamSynchronize(d->stream));

@@ -261,7 +261,8 @@ struct ItemCtx {
   const PF_CONST PlaneCoef<R>* tab;
   Copy src, dst;
   uint32_t* jf;  // the item's classification word (written by the phi-sweep)
-  uint32_t* jn;  // the step's count of light items
+  uint32_t* jc;  // the step's counts (count_word)
+  int slot;      // this item's slot of each count
   DevDomain* dw;  // the descriptor, for the one word the sweeps write (pflag_ok)
 };
 
@@ -296,10 +297,16 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   const int local = item - first_item(first, di);
   X.dw = to_const(doms)[di];
   X.jf = static_cast<uint32_t*>(d.jfree) + local;
-  X.jn = static_cast<uint32_t*>(d.jfree) + d.nitems;
+  X.jc = static_cast<uint32_t*>(d.jfree) + count_base(d.nitems);
+  X.slot = local % kCountSlots;
   if (jsel >= 0) {  // uniform over the work group
     bool light = item_jfree(*to_const(X.jf));
-    if (light) light = (uint64_t)*to_const(X.jn) * 100 >= (uint64_t)d.nitems * kBulkMinPct;
+    if (light) {
+      uint32_t n = 0;
+#pragma unroll
+      for (int sl = 0; sl < kCountSlots; ++sl) n += to_const(X.jc)[count_word(kCountLight, sl)];
+      light = (uint64_t)n * 100 >= (uint64_t)d.nitems * kBulkMinPct;
+    }
     if (light != (jsel == 1)) return false;
   }
   X.dp = &d;
@@ -648,7 +655,7 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
           const uint32_t w = (uint32_t)s_jw[0] | (uint32_t)s_jw[1] << 8 | (uint32_t)s_jw[2] << 16 |
                              (uint32_t)s_jw[3] << 24;
           *to_global(X.jf) = w;
-          if (item_jfree(w)) atomicAdd(X.jn, 1u);
+          if (item_jfree(w)) atomicAdd(X.jc + count_word(kCountLight, X.slot), 1u);
         }
       }
     }
@@ -717,12 +724,12 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
       static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
           (uint8_t)(fixed | kSame);
       dd_mark_flags(dd, X.dw);
-      atomicAdd(X.jn + 1, 1u);
+      atomicAdd(X.jc + count_word(kCountFixed, X.slot), 1u);
       uint32_t w = 0;
       if constexpr (sizeof(R) == 8) {  // the mu-sweep's classification (item_jfree)
         const uint32_t b = P.mu_frozen ? 0u : (!P.antitrap ? 3u : (fixed == LQ ? 2u : 1u));
         w = b * 0x01010101u;
-        if (item_jfree(w)) atomicAdd(X.jn, 1u);
+        if (item_jfree(w)) atomicAdd(X.jc + count_word(kCountLight, X.slot), 1u);
       }
       *to_global(X.jf) = w | kBulkDone;
     }
@@ -1220,6 +1227,10 @@ __device__ __forceinline__ R pure_coef(const PF_CONST PlaneCoef<R>& C, int a, in
 // zero sum stays +0 before and after that term); the chi sum's reciprocal
 // is the plane's rchip.  For every finite state mu^{n+1} is bitwise the
 // other bodies', from a third of the bytes and a quarter of the arithmetic.
+// Planes of mu^n each thread of mu_pure_body has in flight ahead of the
+// one it evaluates.
+constexpr int kPureAhead = 4;
+
 template <typename R>
 __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32_t* first, int ndom,
                                              int total) {
@@ -1227,6 +1238,7 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
   // the scalar cache, and a scalar load per value and plane would put a
   // round trip to L2 into every plane)
   __shared__ R s_cf[kMaxZc][kPureCoef];
+  __shared__ LdsMu<R> s_m[2];  // mu^n of plane k with the halo ring, by plane parity
   const int t = threadIdx.x;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     ItemCtx<R> X;
@@ -1235,17 +1247,16 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
     if (!P.shortcuts || P.mu_frozen) continue;  // uniform
     const int a = mu_pure_phase(*X.dp, chunk_id(*X.dp, X.G));
     if (a < 0) continue;  // uniform
-    if (t == 0) atomicAdd(X.jn + 2, 1u);
+    if (t == 0) atomicAdd(X.jc + count_word(kCountPure, X.slot), 1u);
     const TileGeo& G = X.G;
-    __syncthreads();  // the previous item's coefficients are consumed
-    for (int i = t; i < (G.z1 - G.z0) * kPureCoef; i += blockDim.x)
-      s_cf[i / kPureCoef][i % kPureCoef] = pure_coef<R>(X.tab[G.z0 + i / kPureCoef], a, i % kPureCoef);
-    __syncthreads();
-    if (!G.valid) continue;  // no barriers below
     const Geo& g = X.g;
     const Copy& src = X.src;
     const Copy& dst = X.dst;
     const R inv_dx = (R)P.inv_dx;
+    const int z0 = G.z0, z1 = G.z1;
+    __syncthreads();  // the previous item's LDS planes and coefficients are consumed
+    for (int i = t; i < (z1 - z0) * kPureCoef; i += blockDim.x)
+      s_cf[i / kPureCoef][i % kPureCoef] = pure_coef<R>(X.tab[z0 + i / kPureCoef], a, i % kPureCoef);
     R ha;  // h_a of a cell holding e_a (1)
     {
       R e[NP], h[NP];
@@ -1254,70 +1265,76 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
       mu_cell_h<R>(e, h);
       ha = h[a];
     }
-    const int gx = G.x0 + G.lx, gy = G.y0 + G.ly;
-    const uint32_t row = (uint32_t)gy * (uint32_t)g.pitch, rs = sizeof(R);
-    // lateral neighbours: x-1, x+1, y-1, y+1 (periodic)
-    const uint32_t nb[4] = {(row + g.xm(gx)) * rs, (row + g.xp(gx)) * rs,
-                            ((uint32_t)g.ym(gy) * g.pitch + gx) * rs,
-                            ((uint32_t)g.yp(gy) * g.pitch + gx) * rs};
+    // Ring of mu^n loads, slot p % kPureAhead for plane p: the own column
+    // for planes z0 .. z1 (plane z1 feeds the z face above the last plane;
+    // zc gives the mirror or the ghost plane there) and this thread's halo
+    // cell for planes z0 .. z1-1.  Only these loads go to global memory, so
+    // a wait for plane k's values never waits for the loads issued after
+    // them (the memory counter is in order).
+    R ro[kPureAhead][NM], rh[kPureAhead][NM];
+    const bool halo = G.halo_c >= 0;
+    const auto fetch = [&](int p, R o[NM], R hv[NM]) {
+      const int pc = g.zc(p);
+      o[0] = ldg<R>(src.at(4, pc), G.own_b);
+      o[1] = ldg<R>(src.at(5, pc), G.own_b);
+      if (halo && p < z1) {
+        hv[0] = ldg<R>(src.at(4, pc), G.halo_b);
+        hv[1] = ldg<R>(src.at(5, pc), G.halo_b);
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < kPureAhead; ++u)
+      if (z0 + u <= z1) fetch(z0 + u, ro[u], rh[u]);
     // the z face below z0 as the sweep of the plane below evaluates it
-    const int kb = G.z0 - 1;
-    R m[NM] = {ldg<R>(src.at(4, G.z0), G.own_b), ldg<R>(src.at(5, G.z0), G.own_b)};
     R Pzl[NM] = {R(0), R(0)};
+    const int kb = z0 - 1;
     if (g.zface(kb)) {
       const R mb[NM] = {ldg<R>(src.at(4, g.zc(kb)), G.own_b), ldg<R>(src.at(5, g.zc(kb)), G.own_b)};
 #pragma unroll
-      for (int q = 0; q < NM; ++q) Pzl[q] = mu_face_flux<R>(X.tab[kb].MpZ[a][q], mb[q], m[q], inv_dx);
+      for (int q = 0; q < NM; ++q)
+        Pzl[q] = mu_face_flux<R>(X.tab[kb].MpZ[a][q], mb[q], ro[0][q], inv_dx);
     }
-    // Loads of plane k: mu^n of the own column above it and of the lateral
-    // neighbours.  Two buffers alternate so that the loads of plane k+1 are
-    // issued before plane k is evaluated and stored, and no value in flight
-    // is copied between registers (which would wait for it, and for the
-    // stores issued before it, at once).
-    struct Buf {
-      R up[NM];
-      R L[4][NM];
-    };
-    const auto issue = [&](int k, Buf& b) {
-      const int k1 = g.zp(k);
-      b.up[0] = ldg<R>(src.at(4, k1), G.own_b);
-      b.up[1] = ldg<R>(src.at(5, k1), G.own_b);
+    const int ox = G.lx + 1, oy = G.ly + 1;
+    for (int k0 = z0; k0 < z1; k0 += kPureAhead) {
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        b.L[n][0] = ldg<R>(src.at(4, k), nb[n]);
-        b.L[n][1] = ldg<R>(src.at(5, k), nb[n]);
-      }
-    };
-    const auto plane = [&](int k, const Buf& b) {
-      const R* cf = s_cf[k - G.z0];
-      const bool zf = g.zface(k);
+      for (int u = 0; u < kPureAhead; ++u) {
+        const int k = k0 + u;
+        if (k >= z1) break;  // uniform
+        LdsMu<R>& sm = s_m[k & 1];
+        // plane k into LDS; its own value and the one above in registers
+        const R m[NM] = {ro[u][0], ro[u][1]};
+        sm.put(G.own_c, m);
+        if (halo) sm.put(G.halo_c, rh[u]);
+        const int u1 = (u + 1) % kPureAhead;  // a constant once unrolled
+        const R up[NM] = {ro[u1][0], ro[u1][1]};
+        // slot u is free: plane k + kPureAhead
+        if (k + kPureAhead <= z1) fetch(k + kPureAhead, ro[u], rh[u]);
+        __syncthreads();  // plane k visible (the buffer of plane k-2 was consumed)
+        if (G.valid) {
+          const R* cf = s_cf[k - z0];
+          const bool zf = g.zface(k);
+          R L[4][NM];
+          sm.get(G.ci(ox - 1, oy), L[0]);
+          sm.get(G.ci(ox + 1, oy), L[1]);
+          sm.get(G.ci(ox, oy - 1), L[2]);
+          sm.get(G.ci(ox, oy + 1), L[3]);
 #pragma unroll
-      for (int q = 0; q < NM; ++q) {
-        const R Mxy = cf[q];
-        const R fxl = mu_face_flux<R>(Mxy, b.L[0][q], m[q], inv_dx);
-        const R fxu = mu_face_flux<R>(Mxy, m[q], b.L[1][q], inv_dx);
-        const R fyl = mu_face_flux<R>(Mxy, b.L[2][q], m[q], inv_dx);
-        const R fyu = mu_face_flux<R>(Mxy, m[q], b.L[3][q], inv_dx);
-        const R Pzu = zf ? mu_face_flux<R>(cf[2 + q], m[q], b.up[q], inv_dx) : R(0);
-        R div = R(0);
-        div += fxu - fxl;
-        div += fyu - fyl;
-        div = (div + (Pzu - Pzl[q])) * inv_dx;
-        Pzl[q] = Pzu;
-        const R sq = mu_pure_src<R>(ha, cf[6 + q], cf[8 + q], m[q]);
-        stg<R>(dst.at(4 + q, k), G.own_b, mu_cell_out<R>(P, div, sq, cf[4 + q], m[q]));
-      }
-      m[0] = b.up[0];
-      m[1] = b.up[1];
-    };
-    Buf A, B;
-    issue(G.z0, A);
-    for (int k = G.z0; k < G.z1; k += 2) {
-      if (k + 1 < G.z1) issue(k + 1, B);
-      plane(k, A);
-      if (k + 1 < G.z1) {
-        if (k + 2 < G.z1) issue(k + 2, A);
-        plane(k + 1, B);
+          for (int q = 0; q < NM; ++q) {
+            const R Mxy = cf[q];
+            const R fxl = mu_face_flux<R>(Mxy, L[0][q], m[q], inv_dx);
+            const R fxu = mu_face_flux<R>(Mxy, m[q], L[1][q], inv_dx);
+            const R fyl = mu_face_flux<R>(Mxy, L[2][q], m[q], inv_dx);
+            const R fyu = mu_face_flux<R>(Mxy, m[q], L[3][q], inv_dx);
+            const R Pzu = zf ? mu_face_flux<R>(cf[2 + q], m[q], up[q], inv_dx) : R(0);
+            R div = R(0);
+            div += fxu - fxl;
+            div += fyu - fyl;
+            div = (div + (Pzu - Pzl[q])) * inv_dx;
+            Pzl[q] = Pzu;
+            const R sq = mu_pure_src<R>(ha, cf[6 + q], cf[8 + q], m[q]);
+            stg<R>(dst.at(4 + q, k), G.own_b, mu_cell_out<R>(P, div, sq, cf[4 + q], m[q]));
+          }
+        }
       }
     }
   }
