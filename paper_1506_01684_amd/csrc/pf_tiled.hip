@@ -399,24 +399,31 @@ __device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, i
   return ok ? a : -1;
 }
 
-// The phase a when this step's phi_bulk_kernel kept the item's chunk and
-// all 26 neighbouring chunks in phase a (their flags in the copy being
-// written read a | kSame; the sweep itself never writes kSame), else -1.
-// Then phi^n = phi^{n+1} = e_a on every cell the mu-sweep reads for the
-// item: the chunks are pure in phi^n and copied unchanged, and the cells
-// read lie at most one cell outside the chunk.  Uniform over the group.
+// The phase a when the item's chunk and its 26 neighbours hold phase a
+// purely both before and after this step's phi-sweep (the flags of the
+// source copy, valid unless withdrawn, and those the sweep has just written
+// for the copy it wrote), else -1.  Then phi^n = phi^{n+1} = e_a on every
+// cell the mu-sweep reads for the item (at most one cell outside the
+// chunk; at the z ends the mirror adds nothing, the ghost plane of a
+// Dirichlet top is liquid).  Uniform over the group.
 template <typename DD>
 __device__ __forceinline__ int mu_pure_phase(const DD& d, const ChunkId& c) {
-  const PF_CONST uint8_t* f = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src ^ 1]));
-  const int own = f[chunk_index(d, c)];
-  const int a = flag_phase(own);
-  if (a >= NP || own != (a | kSame)) return -1;
+  if (!d.pflag_ok[d.cur_src]) return -1;
+  const PF_CONST uint8_t* f0 = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src]));
+  const PF_CONST uint8_t* f1 = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src ^ 1]));
+  const int idx = chunk_index(d, c);
+  const int a = flag_phase(f1[idx]);
+  if (a >= NP || flag_phase(f0[idx]) != a) return -1;
   if (c.iz + 1 >= d.nzc && d.top_bc && a != LQ) return -1;
   int v[27];
-  neighbour_flags(d, f, c, v);
   bool ok = true;
+  neighbour_flags(d, f1, c, v);  // after the sweep first: most items fail there
 #pragma unroll
-  for (int i = 0; i < 27; ++i) ok = ok && v[i] == own;
+  for (int i = 0; i < 27; ++i) ok = ok && flag_phase(v[i]) == a;
+  if (!ok) return -1;
+  neighbour_flags(d, f0, c, v);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) ok = ok && flag_phase(v[i]) == a;
   return ok ? a : -1;
 }
 

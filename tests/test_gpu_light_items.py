@@ -74,8 +74,8 @@ def test_light_items_reported_only_for_the_fp64_tiled_sweep():
 def test_bulk_chunks_are_copied_exactly(prec, aniso, top_bc):
     """Chunks that hold one pure phase, with all their neighbours, at a fixed
     point are copied by the phi bulk shortcut: most of a tall liquid column
-    is; the mu-sweep of a kept chunk whose neighbours were all kept reads mu
-    alone.  The result equals the shortcuts-off run bitwise (with the
+    is; the mu-sweep of a chunk that, with all its neighbours, holds one
+    pure phase before and after the phi-sweep reads mu alone.  The result equals the shortcuts-off run bitwise (with the
     Dirichlet top too, whose liquid ghost allows only liquid chunks at the
     top)."""
     shape = (96, 24, 70)
@@ -87,8 +87,9 @@ def test_bulk_chunks_are_copied_exactly(prec, aniso, top_bc):
     log(f"bulk {prec} aniso={aniso} top_bc={top_bc}: fixed items {da['fixed_items']} of "
         f"{da['work_items']}, mu from mu alone {da['mu_pure_items']}")
     assert da["fixed_items"] > da["work_items"] // 3 and db["fixed_items"] == 0
-    # the chunks kept with all their neighbours: mu from mu alone
-    assert 0 < da["mu_pure_items"] <= da["fixed_items"] and db["mu_pure_items"] == 0
+    # chunks pure, with all their neighbours, before and after the phi-sweep:
+    # mu from mu alone
+    assert 0 < da["mu_pure_items"] <= da["work_items"] and db["mu_pure_items"] == 0
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
