@@ -472,7 +472,8 @@ def main():
     aniso = "true" if args.workload == "c3" else "false"
     # the FP64 mu-sweep is two launches (items with and without the
     # anti-trapping current); the roofline covers the whole sweep
-    kname = (("mu_tiled_f64+mu_bulk_f64" if real == "double" else "mu_tiled_f32") if dom == "mu"
+    kname = (("mu_pure_f64+mu_tiled_f64+mu_bulk_f64" if real == "double" else "mu_pure_f32+mu_tiled_f32")
+             if dom == "mu"
              else f"phi_bulk_kernel<{real}>+phi_tiled_f{64 if real == 'double' else 32}"
                   f"{'_aniso' if aniso == 'true' else ''}")
     traffic = recorded_traffic(kname, args.workload) if args.variant == 1 else None
