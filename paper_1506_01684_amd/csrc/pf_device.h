@@ -135,6 +135,8 @@ struct DevDomain {
   int32_t pflag_ok[2];        // pflag[c] describes the state held in copy c
   void* pflag[2];             // uint8 per tile and z chunk [iz][iy][ix]: the phase all
                               // cells of the chunk hold purely in copy c, 0xFF if none
+  void* pends[2];             // uint8 per chunk, same order: the pure phase of its
+                              // bottom plane (low nibble) and top plane (high), 0xF if none
   double dt, dx;
   double eps, TE, T0, G, v, zoff;
   double chi0[NP][NM], chi1[NP][NM], c0[NP][NM], c1[NP][NM];

@@ -123,8 +123,8 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, then the counts
   off = align_up(off + sizeof(uint32_t) * ((size_t)count_base(T.blocks()) + kCountWords), kAlign);
   L.pflag_bytes = align_up((size_t)T.ntx * T.nty * T.nzc, kAlign);
-  L.off_pflag = off;  // the pure-phase flags of each copy's state
-  off += 2 * L.pflag_bytes;
+  L.off_pflag = off;  // the pure-phase flags of each copy's state, then those of the
+  off += 4 * L.pflag_bytes;  // chunks' end planes
   L.off_mesh = off;  // triangle counter of pf_mesh_phase
   off = align_up(off + sizeof(unsigned long long), kAlign);
   L.off_partials = off;
@@ -428,6 +428,8 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
   h.nitems = d->T.blocks();
   h.pflag[0] = d->base + L.off_pflag;
   h.pflag[1] = d->base + L.off_pflag + L.pflag_bytes;
+  h.pends[0] = d->base + L.off_pflag + 2 * L.pflag_bytes;
+  h.pends[1] = d->base + L.off_pflag + 3 * L.pflag_bytes;
   h.pflag_ok[0] = h.pflag_ok[1] = 0;  // the host mirror never vouches for the flags
   h.dx = desc->dx;
   int32_t first[2] = {0, d->T.blocks()};

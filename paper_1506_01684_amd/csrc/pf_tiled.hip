@@ -360,13 +360,17 @@ __device__ __forceinline__ void dd_mark_flags(const DD& d, DevDomain* dw) {
   to_global(&dw->pflag_ok[d.cur_src ^ 1])[0] = 1;
 }
 
-// Flag bytes of a chunk's 27-chunk neighbourhood (periodic in x and y; a z
-// neighbour outside the domain reads the chunk itself), all loaded before
-// any is tested, so that the loads overlap instead of taking one round trip
-// each.
+// The flags that decide whether the cells a chunk's stencils read around
+// it hold one pure phase: of the chunk and its 8 lateral neighbours the
+// whole-chunk flag, of the 9 chunks below and the 9 above the end-plane flag
+// (only their top / bottom plane lies within one cell of the chunk).
+// Periodic in x and y; a z neighbour outside the domain reads the chunk
+// itself (the mirror repeats its own end plane).  All 27 bytes are loaded
+// before any is tested, so that the loads overlap instead of taking one
+// round trip each.
 template <typename DD>
-__device__ __forceinline__ void neighbour_flags(const DD& d, const PF_CONST uint8_t* f,
-                                                const ChunkId& c, int v[27]) {
+__device__ __forceinline__ void halo_flags(const DD& d, const PF_CONST uint8_t* f,
+                                           const PF_CONST uint8_t* e, const ChunkId& c, int v[27]) {
   int jx[3], jy[3], jz[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -376,55 +380,63 @@ __device__ __forceinline__ void neighbour_flags(const DD& d, const PF_CONST uint
     jz[i] = z < 0 || z >= d.nzc ? c.iz : z;
   }
 #pragma unroll
-  for (int i = 0; i < 27; ++i) v[i] = f[(jz[i / 9] * d.nty + jy[(i / 3) % 3]) * d.ntx + jx[i % 3]];
+  for (int i = 0; i < 27; ++i)
+    v[i] = (i / 9 == 1 ? f : e)[(jz[i / 9] * d.nty + jy[(i / 3) % 3]) * d.ntx + jx[i % 3]];
+}
+// Whether halo_flags v all say phase a (below: top plane; lateral: whole
+// chunk; above: bottom plane).
+__device__ __forceinline__ bool halo_is(const int v[27], int a) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int p = i < 9 ? v[i] >> 4 : (i < 18 ? flag_phase(v[i]) : v[i] & 0x0F);
+    ok = ok && p == a;
+  }
+  return ok;
 }
 
 // The phase of a bulk chunk that may be copied, or -1 (uniform over the
-// group): the chunk and its 26 neighbours hold phase a purely (at the z ends
-// the mirror adds nothing; the ghost plane of a Dirichlet top is liquid),
-// and every plane of the chunk marks a as a fixed point.
+// group): the chunk holds phase a purely, so do the cells its stencils
+// read around it (halo_flags; the ghost plane of a Dirichlet top is
+// liquid), and every plane of the chunk marks a as a fixed point.
 template <typename DD, typename TAB>
 __device__ __forceinline__ int bulk_fixed_phase(const DD& d, const ChunkId& c, int z0,
                                                 const TAB* tab) {
   if (!d.pflag_ok[d.cur_src]) return -1;
   const PF_CONST uint8_t* f = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src]));
+  const PF_CONST uint8_t* e = to_const(static_cast<const uint8_t*>(d.pends[d.cur_src]));
   const int a = flag_phase(f[chunk_index(d, c)]);
   if (a >= NP) return -1;
   if (c.iz + 1 >= d.nzc && d.top_bc && a != LQ) return -1;
   int v[27];
-  neighbour_flags(d, f, c, v);
-  bool ok = ((tab[z0].chunk_fixed >> a) & 1) != 0;
-#pragma unroll
-  for (int i = 0; i < 27; ++i) ok = ok && flag_phase(v[i]) == a;
+  halo_flags(d, f, e, c, v);
+  const bool ok = ((tab[z0].chunk_fixed >> a) & 1) != 0 && halo_is(v, a);
   return ok ? a : -1;
 }
 
-// The phase a when the item's chunk and its 26 neighbours hold phase a
-// purely both before and after this step's phi-sweep (the flags of the
-// source copy, valid unless withdrawn, and those the sweep has just written
-// for the copy it wrote), else -1.  Then phi^n = phi^{n+1} = e_a on every
-// cell the mu-sweep reads for the item (at most one cell outside the
-// chunk; at the z ends the mirror adds nothing, the ghost plane of a
-// Dirichlet top is liquid).  Uniform over the group.
+// The phase a when the item's chunk and the cells its stencils read around
+// it hold phase a purely both before and after this step's phi-sweep (the
+// flags of the source copy, valid unless withdrawn, and those the sweep has
+// just written for the copy it wrote), else -1.  Then phi^n = phi^{n+1} =
+// e_a on every cell the mu-sweep reads for the item (at the z ends the
+// mirror adds nothing, the ghost plane of a Dirichlet top is liquid).
+// Uniform over the group.
 template <typename DD>
 __device__ __forceinline__ int mu_pure_phase(const DD& d, const ChunkId& c) {
   if (!d.pflag_ok[d.cur_src]) return -1;
-  const PF_CONST uint8_t* f0 = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src]));
-  const PF_CONST uint8_t* f1 = to_const(static_cast<const uint8_t*>(d.pflag[d.cur_src ^ 1]));
+  const int s0 = d.cur_src, s1 = d.cur_src ^ 1;
+  const PF_CONST uint8_t* f1 = to_const(static_cast<const uint8_t*>(d.pflag[s1]));
   const int idx = chunk_index(d, c);
   const int a = flag_phase(f1[idx]);
-  if (a >= NP || flag_phase(f0[idx]) != a) return -1;
+  if (a >= NP) return -1;
   if (c.iz + 1 >= d.nzc && d.top_bc && a != LQ) return -1;
   int v[27];
-  bool ok = true;
-  neighbour_flags(d, f1, c, v);  // after the sweep first: most items fail there
-#pragma unroll
-  for (int i = 0; i < 27; ++i) ok = ok && flag_phase(v[i]) == a;
-  if (!ok) return -1;
-  neighbour_flags(d, f0, c, v);
-#pragma unroll
-  for (int i = 0; i < 27; ++i) ok = ok && flag_phase(v[i]) == a;
-  return ok ? a : -1;
+  // after the sweep first: most items fail there
+  halo_flags(d, f1, to_const(static_cast<const uint8_t*>(d.pends[s1])), c, v);
+  if (!halo_is(v, a)) return -1;
+  halo_flags(d, to_const(static_cast<const uint8_t*>(d.pflag[s0])),
+             to_const(static_cast<const uint8_t*>(d.pends[s0])), c, v);
+  return halo_is(v, a) ? a : -1;
 }
 
 // The phase a cell holds purely (phi = e_a exactly), or -1.
@@ -461,6 +473,7 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
   __shared__ R s_qy[NP][kMaxFy];
   __shared__ uint8_t s_jw[4];          // per-wave bytes of the item's classification word
   __shared__ int8_t s_pw[4];           // per-wave pure phase of the outputs (pure_phase_flag)
+  __shared__ int8_t s_pe[2][4];        // the same for the first and last plane
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
 
@@ -480,7 +493,9 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
 
     // chunks copied unchanged by phi_bulk_kernel (launched just before)
     if (*to_const(X.jf) & kBulkDone) continue;
-    int po = -2;  // pure phase of this thread's outputs so far (-2: none, -1: mixed)
+    // pure phase of this thread's outputs so far (-2: none, -1: mixed), and
+    // of its outputs on the first and last plane: bytes 0, 1, 2 hold each + 2
+    int pst = 0;
 
     // liquid content of every phi^n cell this item loads (item_jfree; the
     // FP64 mu-sweep only)
@@ -629,7 +644,10 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
           stg<R>(dst.at(a, k), G.own_b, o[a]);
         }
         const int pa = pure_phase(o);
-        po = po == -2 ? pa : (po == pa ? po : -1);
+        const int po = (pst & 0xFF) - 2;
+        pst = (pst & ~0xFF) | ((po == -2 ? pa : (po == pa ? po : -1)) + 2);
+        if (k == G.z0) pst = (pst & ~0xFF00) | (pa + 2) << 8;
+        if (k == G.z1 - 1) pst = (pst & ~0xFF0000) | (pa + 2) << 16;
       }
 #pragma unroll
       for (int a = 0; a < NP; ++a) Qzl[a] = Qzu[a];
@@ -639,24 +657,33 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
     // end of the item: the pure phase of its outputs (for the next step's
     // bulk shortcut) and, in FP64, the mu-sweep's classification
     {
-      const int wp = wave_pure_phase(po);
+      const int wp = wave_pure_phase((pst & 0xFF) - 2);
+      const int we0 = wave_pure_phase((pst >> 8 & 0xFF) - 2), we1 = wave_pure_phase((pst >> 16) - 2);
       uint32_t b = 0;
       if constexpr (CLASSIFY)
         if (shortcut && !P.mu_frozen)
           b = !P.antitrap ? 3u : (__all(no_liq) ? 1u : 0u) | (__all(only_liq) ? 2u : 0u);
       if (lane == 0) {
         s_pw[wave] = (int8_t)wp;
+        s_pe[0][wave] = (int8_t)we0;
+        s_pe[1][wave] = (int8_t)we1;
         s_jw[wave] = (uint8_t)b;
       }
       __syncthreads();
       if (t == 0) {
-        int ph = -2;
-        for (int w = 0; w < 4; ++w) {
-          const int v = s_pw[w];
-          ph = v == -2 ? ph : (ph == -2 || ph == v ? v : -1);
-        }
-        static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
-            ph >= 0 ? (uint8_t)ph : (uint8_t)0xFF;
+        const auto group = [](const int8_t* p) {
+          int ph = -2;
+          for (int w = 0; w < 4; ++w) {
+            const int v = p[w];
+            ph = v == -2 ? ph : (ph == -2 || ph == v ? v : -1);
+          }
+          return ph;
+        };
+        const int ph = group(s_pw), e0 = group(s_pe[0]), e1 = group(s_pe[1]);
+        const int idx = chunk_index(dd, cid);
+        static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[idx] = ph >= 0 ? (uint8_t)ph : (uint8_t)0xFF;
+        static_cast<uint8_t*>(dd.pends[dd.cur_src ^ 1])[idx] =
+            (uint8_t)((e1 >= 0 ? e1 : 0xF) << 4 | (e0 >= 0 ? e0 : 0xF));
         dd_mark_flags(dd, X.dw);
         if constexpr (CLASSIFY) {
           const uint32_t w = (uint32_t)s_jw[0] | (uint32_t)s_jw[1] << 8 | (uint32_t)s_jw[2] << 16 |
@@ -730,6 +757,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
     if (t == 0) {
       static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
           (uint8_t)(fixed | kSame);
+      static_cast<uint8_t*>(dd.pends[dd.cur_src ^ 1])[chunk_index(dd, cid)] = (uint8_t)(fixed << 4 | fixed);
       dd_mark_flags(dd, X.dw);
       atomicAdd(X.jc + count_word(kCountFixed, X.slot), 1u);
       uint32_t w = 0;
