@@ -144,3 +144,87 @@ def test_bulk_skip_survives_a_checkpoint_save():
     (a, da), (b, _) = out[1], out[0]
     assert da["fixed_items"] > 0 and da["mu_pure_items"] > 0
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _chunk_layout(shape):
+    """Tile and z chunk of the tiled sweeps (the rule the library applies)."""
+    nz, ny, nx = shape
+    tx = 64 if nx >= 48 else 32
+    ty = 256 // tx
+    ntx, nty = -(-nx // tx), -(-ny // ty)
+    zc = min(32, max(8, nz * ntx * nty // 2048), nz)
+    return tx, ty, zc
+
+
+def _chunk_purity(phi, tx, ty, zc):
+    """Per chunk [iz, iy, ix]: the phase all its cells hold purely, and the
+    same for its first and its last plane (-1: none)."""
+    nz, ny, nx = phi.shape[1:]
+    cell = np.full((nz, ny, nx), -1)
+    for a in range(4):
+        others = np.ones((nz, ny, nx), bool)
+        for b in range(4):
+            if b != a:
+                others &= phi[b] == 0.0
+        cell[(phi[a] == 1.0) & others] = a
+
+    def common(block):
+        v = np.unique(block)
+        return int(v[0]) if len(v) == 1 and v[0] >= 0 else -1
+    shp = (-(-nz // zc), -(-ny // ty), -(-nx // tx))
+    whole, first, last = (np.full(shp, -1) for _ in range(3))
+    for iz, iy, ix in np.ndindex(*shp):
+        z0, y0, x0 = iz * zc, iy * ty, ix * tx
+        z1 = min(z0 + zc, nz)
+        blk = cell[z0:z1, y0:y0 + ty, x0:x0 + tx]
+        whole[iz, iy, ix] = common(blk)
+        first[iz, iy, ix] = common(blk[0])
+        last[iz, iy, ix] = common(blk[-1])
+    return whole, first, last
+
+
+def _expected_pure_items(before, after, top_bc):
+    """Items whose chunk and the cells its stencils read around it hold one
+    phase purely before and after the step: the chunk and its lateral
+    neighbours whole, the chunks below by their last plane, those above by
+    their first (periodic in x and y; outside the domain in z the chunk
+    itself), liquid only at a Dirichlet top."""
+    nzc, nty, ntx = before[0].shape
+    n = 0
+    for iz, iy, ix in np.ndindex(nzc, nty, ntx):
+        a = after[0][iz, iy, ix]
+        if a < 0 or (iz == nzc - 1 and top_bc and a != 3):
+            continue
+        ok = True
+        for whole, first, last in (before, after):
+            for dz, dy, dx in np.ndindex(3, 3, 3):
+                jz = iz + dz - 1
+                jz = iz if jz < 0 or jz >= nzc else jz
+                j = (jz, (iy + dy - 1) % nty, (ix + dx - 1) % ntx)
+                v = (last, whole, first)[dz][j]
+                ok = ok and v == a
+        n += ok
+    return n
+
+
+@pytest.mark.parametrize("prec,aniso,top_bc", [("fp64", False, 0), ("fp32", True, 1)])
+def test_pure_item_count_matches_the_fields(prec, aniso, top_bc):
+    """The mu-sweep's pure items of one step are exactly the chunks that the
+    fields before and after the step make pure, end planes included (a
+    count from the fields read back, computed here)."""
+    shape = (96, 24, 70)
+    p = pfinputs.p0_params(solid_height=10, delta_sl=0.05 if aniso else 0.0)
+    p["top_bc"] = top_bc
+    p["dt"] = oracle.default_dt(p, shape)
+    d = gpu_domain(shape, p, prec, 1, voronoi=(4, 7, 10))
+    d.step(8)
+    phi0, _ = d.read()
+    d.step(1)
+    phi1, _ = d.read()
+    dg = d.diagnostics()
+    d.close()
+    tx, ty, zc = _chunk_layout(shape)
+    want = _expected_pure_items(_chunk_purity(phi0, tx, ty, zc), _chunk_purity(phi1, tx, ty, zc), top_bc)
+    log(f"pure items {prec} top_bc={top_bc}: {dg['mu_pure_items']} (fields: {want}) of {dg['work_items']}")
+    assert 0 < want < dg["work_items"]
+    assert dg["mu_pure_items"] == want
