@@ -326,12 +326,15 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
 // chunk's new cells hold purely (0..3) or 0xFF, in the flags of the copy it
 // writes (pflag); the prologue withdraws a copy's flags before it is
 // rewritten or after a window shift, and the sweep vouches for them again
-// (pflag_ok) when it has written them.  A later sweep may then copy a chunk
-// unchanged when it and its 26 neighbours (periodic in x and y; at the z
-// ends the mirror adds nothing, a Dirichlet ghost is liquid) hold the same
-// pure phase and every plane of the chunk marks that phase as a fixed point:
-// every face of every cell then has zero normal differences, so each cell
-// is a pure cell with A = 0, which the per-cell shortcut keeps exactly.
+// (pflag_ok) when it has written them; beside them, the pure phase of each
+// chunk's first and last plane (pends).  A later sweep may then copy a
+// chunk unchanged when it and the cells its stencils read around it
+// (halo_flags: lateral chunks whole, the end planes of the chunks above and
+// below; at the z ends the mirror adds nothing, a Dirichlet ghost is
+// liquid) hold the same pure phase and every plane of the chunk marks that
+// phase as a fixed point: every face of every cell then has zero normal
+// differences, so each cell is a pure cell with A = 0, which the per-cell
+// shortcut keeps exactly.
 // A copied chunk's flag also carries kSame: both field copies then hold its
 // phi, so when it is fixed again in the next step the copy is not needed.
 constexpr uint8_t kSame = 0x10;
