@@ -281,6 +281,7 @@ struct ItemCtx {
 // chip, which a small share of light items does not repay.
 constexpr uint64_t kBulkMinPct = 60;
 constexpr uint32_t kBulkDone = 0x80000000u;  // item copied by the phi bulk shortcut
+constexpr uint32_t kMuPure = 0x40000000u;    // item taken by mu_pure_* this step
 __device__ __forceinline__ bool item_jfree(uint32_t f) {
   return ((f & (f >> 8) & (f >> 16) & (f >> 24)) & 3u) != 0;
 }
@@ -822,8 +823,8 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
         }
       continue;
     }
-    // items pure in one phase: mu_pure_kernel
-    if (P.shortcuts && mu_pure_phase(*X.dp, chunk_id(*X.dp, G)) >= 0) continue;
+    // items pure in one phase: taken by mu_pure_* (launched first)
+    if (P.shortcuts && (*to_const(X.jf) & kMuPure)) continue;
 
     // lane l of the edge wave takes the lower-edge face of tile row l (x)
     // or tile column l (y), between x0-1 and x0 / y0-1 and y0
@@ -1116,8 +1117,8 @@ __device__ __forceinline__ void mu_bulk_body(DevDomain* const* doms, const int32
     const Copy& src = X.src;  // phi^n (fields 0-3), mu^n (4-5)
     const Copy& dst = X.dst;  // phi^{n+1}, mu^{n+1}
     const R inv_dx = (R)P.inv_dx;
-    // items pure in one phase: mu_pure_kernel
-    if (P.shortcuts && mu_pure_phase(*X.dp, chunk_id(*X.dp, G)) >= 0) continue;
+    // items pure in one phase: taken by mu_pure_* (launched first)
+    if (P.shortcuts && (*to_const(X.jf) & kMuPure)) continue;
     const bool ex_ok = lane < G.ty && G.y0 + lane < g.ny;
     const bool ey_ok = lane < G.tx && G.x0 + lane < g.nx;
     const int kstart = G.z0 - 1;
@@ -1285,7 +1286,11 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
     if (!P.shortcuts || P.mu_frozen) continue;  // uniform
     const int a = mu_pure_phase(*X.dp, chunk_id(*X.dp, X.G));
     if (a < 0) continue;  // uniform
-    if (t == 0) atomicAdd(X.jc + count_word(kCountPure, X.slot), 1u);
+    if (t == 0) {
+      atomicAdd(X.jc + count_word(kCountPure, X.slot), 1u);
+      // for the other mu kernels of the step (the phi-sweep rewrote the word)
+      *to_global(X.jf) = *to_const(X.jf) | kMuPure;
+    }
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const Copy& src = X.src;
