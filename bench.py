@@ -470,9 +470,9 @@ def main():
     achieved = main_run[f"{dom}_gbs"]
     real = "double" if main_run["prec"] == "fp64" else "float"
     aniso = "true" if args.workload == "c3" else "false"
-    # the FP64 mu-sweep is two launches (items with and without the
-    # anti-trapping current); the roofline covers the whole sweep
-    kname = (("mu_pure_f64+mu_tiled_f64+mu_bulk_f64" if real == "double" else "mu_pure_f32+mu_tiled_f32")
+    # the mu-sweep is two launches (FP64: pure and light items, then the
+    # rest; FP32: pure items, then the rest); the roofline covers the sweep
+    kname = (("mu_light_f64+mu_tiled_f64" if real == "double" else "mu_pure_f32+mu_tiled_f32")
              if dom == "mu"
              else f"phi_bulk_kernel<{real}>+phi_tiled_f{64 if real == 'double' else 32}"
                   f"{'_aniso' if aniso == 'true' else ''}")

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m), m the mean.  The
     // projection returns e_a exactly when every y_b stays below
     // y_a - 1 = rate_a m; the margin covers FP32 rounding of y.
-    // coefficients of the mu-sweep of pure items (mu_pure_body)
+    // coefficients of the mu-sweep of pure items (mu_pure_item)
     for (int a = 0; a < NP; ++a) {
       for (int q = 0; q < NM; ++q) c.cdl[a][q] = c.cbar[a][q] - c.cbar[LQ][q];
       R e[NP], h[NP];

@@ -281,9 +281,20 @@ struct ItemCtx {
 // chip, which a small share of light items does not repay.
 constexpr uint64_t kBulkMinPct = 60;
 constexpr uint32_t kBulkDone = 0x80000000u;  // item copied by the phi bulk shortcut
-constexpr uint32_t kMuPure = 0x40000000u;    // item taken by mu_pure_* this step
+constexpr uint32_t kMuPure = 0x40000000u;    // item taken by the pure-item body this step
 __device__ __forceinline__ bool item_jfree(uint32_t f) {
   return ((f & (f >> 8) & (f >> 16) & (f >> 24)) & 3u) != 0;
+}
+
+// Whether the FP64 mu-sweep's light body takes the item: no face of it can
+// carry the anti-trapping current, and the split runs this step (uniform).
+template <typename DD, typename CTX>
+__device__ __forceinline__ bool item_light(const DD& d, const CTX& X) {
+  if (!item_jfree(*to_const(X.jf))) return false;
+  uint32_t n = 0;
+#pragma unroll
+  for (int sl = 0; sl < kCountSlots; ++sl) n += to_const(X.jc)[count_word(kCountLight, sl)];
+  return (uint64_t)n * 100 >= (uint64_t)d.nitems * kBulkMinPct;
 }
 
 // jsel < 0: every item; 0: items that need the anti-trapping current;
@@ -300,16 +311,7 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   X.jf = static_cast<uint32_t*>(d.jfree) + local;
   X.jc = static_cast<uint32_t*>(d.jfree) + count_base(d.nitems);
   X.slot = local % kCountSlots;
-  if (jsel >= 0) {  // uniform over the work group
-    bool light = item_jfree(*to_const(X.jf));
-    if (light) {
-      uint32_t n = 0;
-#pragma unroll
-      for (int sl = 0; sl < kCountSlots; ++sl) n += to_const(X.jc)[count_word(kCountLight, sl)];
-      light = (uint64_t)n * 100 >= (uint64_t)d.nitems * kBulkMinPct;
-    }
-    if (light != (jsel == 1)) return false;
-  }
+  if (jsel >= 0 && item_light(d, X) != (jsel == 1)) return false;  // uniform
   X.dp = &d;
   X.G = make_tile<R>(d, local, t);
   if (!X.G.item_ok) return false;  // padding block (uniform)
@@ -800,7 +802,7 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     ItemCtx<R> X;
-    // FP64: the items that need the anti-trapping current (mu_bulk_f64
+    // FP64: the items that need the anti-trapping current (mu_light_f64
     // takes the rest); FP32: every item
     if (!item_setup(doms, first, ndom, item, t, X, sizeof(R) == 8 ? 0 : -1)) continue;
     const TileGeo& G = X.G;
@@ -823,7 +825,7 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
         }
       continue;
     }
-    // items pure in one phase: taken by mu_pure_* (launched first)
+    // items pure in one phase: taken by mu_light_f64 / mu_pure_f32 (launched first)
     if (P.shortcuts && (*to_const(X.jf) & kMuPure)) continue;
 
     // lane l of the edge wave takes the lower-edge face of tile row l (x)
@@ -1098,27 +1100,30 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4)
 // neighbours.  Every face value and the cell stage are the same operations
 // on the same operands as in mu_tiled_body, so both kernels give bitwise
 // the same mu^{n+1} on such an item.
+// The LDS of the light items' body.
 template <typename R>
-__device__ __forceinline__ void mu_bulk_body(DevDomain* const* doms, const int32_t* first, int ndom,
-                                             int total) {
-  __shared__ LdsPhi<R, 1> s_phi;  // phi^n of plane k
-  __shared__ LdsMu<R> s_mu;       // mu^n of plane k
-  __shared__ R s_fx[NM][kMaxFx];
-  __shared__ R s_fy[NM][kMaxFy];
-  const int t = threadIdx.x;
-  const int wave = t >> 6, lane = t & 63;
+struct BulkLds {
+  LdsPhi<R, 1> phi;  // phi^n of plane k
+  LdsMu<R> mu;       // mu^n of plane k
+  R fx[NM][kMaxFx];
+  R fy[NM][kMaxFy];
+};
 
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    ItemCtx<R> X;
-    if (!item_setup(doms, first, ndom, item, t, X, 1)) continue;
+template <typename R>
+__device__ __forceinline__ void mu_bulk_item(const ItemCtx<R>& X, BulkLds<R>& L, int t) {
+  LdsPhi<R, 1>& s_phi = L.phi;
+  LdsMu<R>& s_mu = L.mu;
+  R (*s_fx)[kMaxFx] = L.fx;
+  R (*s_fy)[kMaxFy] = L.fy;
+  const int wave = t >> 6, lane = t & 63;
+  {
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const auto& P = kparams<R>(*X.dp);
     const Copy& src = X.src;  // phi^n (fields 0-3), mu^n (4-5)
     const Copy& dst = X.dst;  // phi^{n+1}, mu^{n+1}
     const R inv_dx = (R)P.inv_dx;
-    // items pure in one phase: taken by mu_pure_* (launched first)
-    if (P.shortcuts && (*to_const(X.jf) & kMuPure)) continue;
+    __syncthreads();  // the previous item's LDS is consumed (it may be a pure item's)
     const bool ex_ok = lane < G.ty && G.y0 + lane < g.ny;
     const bool ey_ok = lane < G.tx && G.x0 + lane < g.nx;
     const int kstart = G.z0 - 1;
@@ -1226,16 +1231,10 @@ __device__ __forceinline__ void mu_bulk_body(DevDomain* const* doms, const int32
   }
 }
 
-// FP64 only: in FP32 the tiled kernel, at four waves per SIMD, is already
-// held to 128 VGPRs and evaluates these items about as fast on its own.
-__global__ __launch_bounds__(kTileThreads) void mu_bulk_f64(DevDomain* const* doms, const int32_t* first,
-                                                            int ndom, int total) {
-  mu_bulk_body<double>(doms, first, ndom, total);
-}
 
 
 // The coefficients of one plane that a cell pure in phase a uses, in the
-// order mu_pure_body stages them, two components each: Mp, MpZ, rchip, and
+// order mu_pure_item stages them, two components each: Mp, MpZ, rchip, and
 // dchi, dcbar of phase a.
 constexpr int kPureCoef = 5 * NM;
 template <typename R>
@@ -1266,31 +1265,41 @@ __device__ __forceinline__ R pure_coef(const PF_CONST PlaneCoef<R>& C, int a, in
 // zero sum stays +0 before and after that term); the chi sum's reciprocal
 // is the plane's rchip.  For every finite state mu^{n+1} is bitwise the
 // other bodies', from a third of the bytes and a quarter of the arithmetic.
-// Planes of mu^n each thread of mu_pure_body has in flight ahead of the
+// Planes of mu^n each thread of mu_pure_item has in flight ahead of the
 // one it evaluates.
 constexpr int kPureAhead = 4;
 
+// The LDS of the pure items' body.
 template <typename R>
-__device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32_t* first, int ndom,
-                                             int total) {
-  // the item's plane coefficients, staged once (the table is too large for
-  // the scalar cache, and a scalar load per value and plane would put a
-  // round trip to L2 into every plane)
-  __shared__ R s_cf[kMaxZc][kPureCoef];
-  __shared__ LdsMu<R> s_m[2];  // mu^n of plane k with the halo ring, by plane parity
-  const int t = threadIdx.x;
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    ItemCtx<R> X;
-    if (!item_setup(doms, first, ndom, item, t, X)) continue;
-    const auto& P = kparams<R>(*X.dp);
-    if (!P.shortcuts || P.mu_frozen) continue;  // uniform
-    const int a = mu_pure_phase(*X.dp, chunk_id(*X.dp, X.G));
-    if (a < 0) continue;  // uniform
-    if (t == 0) {
-      atomicAdd(X.jc + count_word(kCountPure, X.slot), 1u);
-      // for the other mu kernels of the step (the phi-sweep rewrote the word)
-      *to_global(X.jf) = *to_const(X.jf) | kMuPure;
-    }
+struct PureLds {
+  LdsMu<R> m[2];            // mu^n of plane k with the halo ring, by plane parity
+  R cf[kMaxZc][kPureCoef];  // the item's plane coefficients, staged once (the
+                            // table is too large for the scalar cache, and a
+                            // scalar load per value and plane would put a round
+                            // trip to L2 into every plane)
+};
+
+// The pure-item test of the mu-sweep for this item, or -1; a pure item is
+// counted and marked (kMuPure) for the other mu kernels of the step.
+template <typename R>
+__device__ __forceinline__ int mu_pure_take(const ItemCtx<R>& X, int t) {
+  const auto& P = kparams<R>(*X.dp);
+  if (!P.shortcuts || P.mu_frozen) return -1;  // uniform
+  const int a = mu_pure_phase(*X.dp, chunk_id(*X.dp, X.G));
+  if (a >= 0 && t == 0) {
+    atomicAdd(X.jc + count_word(kCountPure, X.slot), 1u);
+    // for the other mu kernels of the step (the phi-sweep rewrote the word)
+    *to_global(X.jf) = *to_const(X.jf) | kMuPure;
+  }
+  return a;  // uniform
+}
+
+template <typename R>
+__device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds<R>& L, int t) {
+  R (*s_cf)[kPureCoef] = L.cf;
+  LdsMu<R>* s_m = L.m;
+  const auto& P = kparams<R>(*X.dp);
+  {
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const Copy& src = X.src;
@@ -1313,21 +1322,23 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
     // zc gives the mirror or the ghost plane there) and this thread's halo
     // cell for planes z0 .. z1-1.  Only these loads go to global memory, so
     // a wait for plane k's values never waits for the loads issued after
-    // them (the memory counter is in order).
+    // them (the memory counter is in order).  The loads are unconditional:
+    // past the item's planes they read planes that zc keeps inside the
+    // buffer, and a thread without a halo cell reads its own column again;
+    // a load on only some paths made the compiler move its value between
+    // registers, waiting for it at once.
     R ro[kPureAhead][NM], rh[kPureAhead][NM];
     const bool halo = G.halo_c >= 0;
+    const uint32_t hb = halo ? G.halo_b : G.own_b;
     const auto fetch = [&](int p, R o[NM], R hv[NM]) {
       const int pc = g.zc(p);
       o[0] = ldg<R>(src.at(4, pc), G.own_b);
       o[1] = ldg<R>(src.at(5, pc), G.own_b);
-      if (halo && p < z1) {
-        hv[0] = ldg<R>(src.at(4, pc), G.halo_b);
-        hv[1] = ldg<R>(src.at(5, pc), G.halo_b);
-      }
+      hv[0] = ldg<R>(src.at(4, pc), hb);
+      hv[1] = ldg<R>(src.at(5, pc), hb);
     };
 #pragma unroll
-    for (int u = 0; u < kPureAhead; ++u)
-      if (z0 + u <= z1) fetch(z0 + u, ro[u], rh[u]);
+    for (int u = 0; u < kPureAhead; ++u) fetch(z0 + u, ro[u], rh[u]);
     // the z face below z0 as the sweep of the plane below evaluates it
     R Pzl[NM] = {R(0), R(0)};
     const int kb = z0 - 1;
@@ -1351,7 +1362,7 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
         const int u1 = (u + 1) % kPureAhead;  // a constant once unrolled
         const R up[NM] = {ro[u1][0], ro[u1][1]};
         // slot u is free: plane k + kPureAhead
-        if (k + kPureAhead <= z1) fetch(k + kPureAhead, ro[u], rh[u]);
+        fetch(k + kPureAhead, ro[u], rh[u]);
         __syncthreads();  // plane k visible (the buffer of plane k-2 was consumed)
         if (G.valid) {
           const R* cf = s_cf[k - z0];
@@ -1383,13 +1394,38 @@ __device__ __forceinline__ void mu_pure_body(DevDomain* const* doms, const int32
   }
 }
 
-__global__ __launch_bounds__(kTileThreads) void mu_pure_f64(DevDomain* const* doms, const int32_t* first,
-                                                            int ndom, int total) {
-  mu_pure_body<double>(doms, first, ndom, total);
-}
+// FP32: the pure items (mu_tiled_f32 takes the rest).
 __global__ __launch_bounds__(kTileThreads) void mu_pure_f32(DevDomain* const* doms, const int32_t* first,
                                                             int ndom, int total) {
-  mu_pure_body<float>(doms, first, ndom, total);
+  __shared__ PureLds<float> L;
+  const int t = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    ItemCtx<float> X;
+    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    const int a = mu_pure_take(X, t);
+    if (a >= 0) mu_pure_item(X, a, L, t);
+  }
+}
+
+// FP64: the pure items, and the light items when the split runs
+// (mu_tiled_f64 takes the rest).  One launch for both, so that the few
+// long light items overlap the many pure ones; they share the LDS, one item
+// at a time.
+__global__ __launch_bounds__(kTileThreads) void mu_light_f64(DevDomain* const* doms, const int32_t* first,
+                                                             int ndom, int total) {
+  constexpr size_t kB = sizeof(BulkLds<double>), kP = sizeof(PureLds<double>);
+  __shared__ __align__(16) unsigned char smem[kB > kP ? kB : kP];
+  const int t = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    ItemCtx<double> X;
+    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    const int a = mu_pure_take(X, t);
+    if (a >= 0) {
+      mu_pure_item(X, a, *reinterpret_cast<PureLds<double>*>(smem), t);
+    } else if (item_light(*X.dp, X)) {
+      mu_bulk_item(X, *reinterpret_cast<BulkLds<double>*>(smem), t);
+    }
+  }
 }
 
 // --------------------------------------------------------------- launches
@@ -1414,17 +1450,15 @@ hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_
   return hipGetLastError();
 }
 
-// The mu-sweep launches over the same items: mu_pure_* takes the items pure
-// in one phase; in FP64 mu_tiled_f64 takes the items whose faces may carry
-// the anti-trapping current, mu_bulk_f64 the rest (all of them go to
-// mu_tiled_f64 in a step with few light ones); in FP32 mu_tiled_f32 takes
-// every other item.
+// The mu-sweep launches over the same items.  FP64: mu_light_f64 takes the
+// items pure in one phase, and the light items when they are the large
+// majority; mu_tiled_f64 the rest.  FP32: mu_pure_f32 takes the pure items,
+// mu_tiled_f32 the rest.
 hipError_t launch_mu_tiled(const LaunchSet& L, int prec, hipStream_t s) {
   const int grid = L.total;
   if (prec == 0) {
-    mu_pure_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    mu_light_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     mu_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
-    mu_bulk_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
   } else {
     mu_pure_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
     mu_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
