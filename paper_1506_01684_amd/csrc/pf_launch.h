@@ -21,6 +21,7 @@ struct LaunchSet {
 
 // Threads per work group of the sweeps (tile tx * ty).
 constexpr int kTileThreads = 256;
+constexpr int kTileWaves = kTileThreads / 64;
 // Most z planes per work item of the tiled sweeps.
 constexpr int kMaxZc = 32;
 

@@ -263,6 +263,7 @@ struct ItemCtx {
   uint32_t* jf;  // the item's classification word (written by the phi-sweep)
   uint32_t* jc;  // the step's counts (count_word)
   int slot;      // this item's slot of each count
+  int local;     // the item's number within its domain
   DevDomain* dw;  // the descriptor, for the one word the sweeps write (pflag_ok)
 };
 
@@ -311,6 +312,7 @@ __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t
   X.jf = static_cast<uint32_t*>(d.jfree) + local;
   X.jc = static_cast<uint32_t*>(d.jfree) + count_base(d.nitems);
   X.slot = local % kCountSlots;
+  X.local = local;
   if (jsel >= 0 && item_light(d, X) != (jsel == 1)) return false;  // uniform
   X.dp = &d;
   X.G = make_tile<R>(d, local, t);
@@ -734,33 +736,41 @@ template <typename R>
 __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const* doms,
                                                                 const int32_t* first, int ndom,
                                                                 int total) {
-  const int t = threadIdx.x;
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  // one item per wave: the test is a few dependent loads, so four items in
+  // flight per work group instead of one
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // scalar
+  const int lane = threadIdx.x & 63;
+  for (int item = blockIdx.x * kTileWaves + wave; item < total; item += gridDim.x * kTileWaves) {
     ItemCtx<R> X;
-    if (!item_setup(doms, first, ndom, item, t, X)) continue;
-    const TileGeo& G = X.G;
+    if (!item_setup(doms, first, ndom, item, lane, X)) continue;  // uniform over the wave
     const auto& P = kparams<R>(*X.dp);
     const PF_CONST DevDomain& dd = *X.dp;
-    const ChunkId cid = chunk_id(dd, G);
-    const int z0 = __builtin_amdgcn_readfirstlane(G.z0);
+    const ChunkId cid = chunk_id(dd, X.G);
+    const int z0 = __builtin_amdgcn_readfirstlane(X.G.z0);
     const int fixed = P.shortcuts ? bulk_fixed_phase(dd, cid, z0, X.tab) : -1;
     if (fixed < 0) {
-      if (t == 0) *to_global(X.jf) = 0u;
+      if (lane == 0) *to_global(X.jf) = 0u;
       continue;
     }
     // unless both copies already hold the chunk (copied or kept in the
-    // previous step too), copy it into the one this step writes
+    // previous step too), copy it into the one this step writes; the wave
+    // takes the tile's columns kTileWaves at a time
     const bool same =
         to_const(static_cast<const uint8_t*>(dd.pflag[dd.cur_src]))[chunk_index(dd, cid)] & kSame;
-    if (!same && G.valid) {
+    if (!same) {
+#pragma unroll 1
+      for (int c = lane; c < kTileThreads; c += 64) {
+        const TileGeo Gc = make_tile<R>(dd, X.local, c);
+        if (!Gc.valid) continue;
 #pragma unroll 4
-      for (int k = G.z0; k < G.z1; ++k) {
-        const V4<R> v = load4<R>(X.src, k, G.own_b);
+        for (int k = Gc.z0; k < Gc.z1; ++k) {
+          const V4<R> v = load4<R>(X.src, k, Gc.own_b);
 #pragma unroll
-        for (int a = 0; a < NP; ++a) stg<R>(X.dst.at(a, k), G.own_b, v.v[a]);
+          for (int a = 0; a < NP; ++a) stg<R>(X.dst.at(a, k), Gc.own_b, v.v[a]);
+        }
       }
     }
-    if (t == 0) {
+    if (lane == 0) {
       static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
           (uint8_t)(fixed | kSame);
       static_cast<uint8_t*>(dd.pends[dd.cur_src ^ 1])[chunk_index(dd, cid)] = (uint8_t)(fixed << 4 | fixed);
@@ -1433,9 +1443,11 @@ __global__ __launch_bounds__(kTileThreads) void mu_light_f64(DevDomain* const* d
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
   const int grid = L.total;
   if (prec == 0)
-    phi_bulk_kernel<double><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    phi_bulk_kernel<double><<<(grid + kTileWaves - 1) / kTileWaves, kTileThreads, 0, s>>>(
+        L.doms, L.first, L.ndom, L.total);
   else
-    phi_bulk_kernel<float><<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    phi_bulk_kernel<float><<<(grid + kTileWaves - 1) / kTileWaves, kTileThreads, 0, s>>>(
+        L.doms, L.first, L.ndom, L.total);
   if (prec == 0) {
     if (aniso)
       phi_tiled_f64_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
