@@ -120,11 +120,6 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
         c.dchiLZ[a][q] = (R)(chiZ[LQ][q] - chiZ[a][q]);
         c.dcbLZ[a][q] = (R)(cbZ[LQ][q] - cbZ[a][q]);
       }
-    // A pure cell (phi = e_a) whose face terms vanish has rhs_a = 0 and
-    // rhs_b = (T/eps) 16/pi^2 gamma_ab, so after the Euler step
-    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m), m the mean.  The
-    // projection returns e_a exactly when every y_b stays below
-    // y_a - 1 = rate_a m; the margin covers FP32 rounding of y.
     // coefficients of the mu-sweep of pure items (mu_pure_item)
     for (int a = 0; a < NP; ++a) {
       for (int q = 0; q < NM; ++q) c.cdl[a][q] = c.cbar[a][q] - c.cbar[LQ][q];
@@ -135,6 +130,11 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
       mu_face_m<R, true>(c, e, c.MpZ[a]);
       for (int q = 0; q < NM; ++q) c.rchip[a][q] = rcp_(mu_cell_chi<R>(c, q, h));
     }
+    // A pure cell (phi = e_a) whose face terms vanish has rhs_a = 0 and
+    // rhs_b = (T/eps) 16/pi^2 gamma_ab, so after the Euler step
+    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m), m the mean.  The
+    // projection returns e_a exactly when every y_b stays below
+    // y_a - 1 = rate_a m; the margin covers FP32 rounding of y.
     c.pure_fixed = 0;
     for (int a = 0; a < NP; ++a) {
       double rhs[NP], m = 0.0;

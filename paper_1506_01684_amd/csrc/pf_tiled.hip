@@ -16,10 +16,17 @@
 //     wherever it is computed;
 //   - the next plane's loads are issued before the face stage and written
 //     to LDS after it, so their latency overlaps the arithmetic.
-// The FP64 mu-sweep runs as two kernels over the same items: items whose
-// faces cannot carry the anti-trapping current (no liquid, or only liquid,
-// around them; classified by the phi-sweep) go to a lighter kernel that
-// stages one phi^n plane and no phi^{n+1} neighbours.
+// Work items may take cheaper bodies that give bitwise the same result:
+//   - phi_bulk_kernel copies (or keeps) the chunks that hold one pure phase
+//     at a fixed point with everything around them, before the phi-sweep;
+//   - the mu-sweep's items that hold one pure phase before and after the
+//     phi-sweep read mu alone (mu_pure_item);
+//   - FP64 items whose faces cannot carry the anti-trapping current (no
+//     liquid, or only liquid, around them; classified by the phi-sweep)
+//     take a lighter body that stages one phi^n plane and no phi^{n+1}
+//     neighbours (mu_bulk_item).
+// The last two run in one FP64 launch (mu_light_f64) before the full
+// kernel, which passes their items over.
 // In the phi-sweep a face enters its two cells' A_a through two shares
 // (face_pq): the one for the cell below the face stays in the registers of
 // the thread that evaluated it, only the one for the cell above goes
@@ -1261,9 +1268,8 @@ __device__ __forceinline__ R pure_coef(const PF_CONST PlaneCoef<R>& C, int a, in
 
 // mu-sweep of the items that mu_pure_phase finds pure in phase a: phi^n =
 // phi^{n+1} = e_a on every cell read, so a thread needs only mu^n of its
-// column and of its four lateral neighbours.  No barriers inside an item:
-// the waves run independently, and the few registers let many of them
-// share a SIMD to cover the load latency.
+// column and of its four lateral neighbours (the latter from an LDS plane
+// that the own columns and the halo ring fill).
 //
 // Same result as the other bodies, operation by operation: each face flux
 // is mu_face_flux of the same two mu values with the coefficient M that
@@ -1275,6 +1281,7 @@ __device__ __forceinline__ R pure_coef(const PF_CONST PlaneCoef<R>& C, int a, in
 // zero sum stays +0 before and after that term); the chi sum's reciprocal
 // is the plane's rchip.  For every finite state mu^{n+1} is bitwise the
 // other bodies', from a third of the bytes and a quarter of the arithmetic.
+
 // Planes of mu^n each thread of mu_pure_item has in flight ahead of the
 // one it evaluates.
 constexpr int kPureAhead = 4;
