@@ -228,3 +228,27 @@ def test_pure_item_count_matches_the_fields(prec, aniso, top_bc):
     log(f"pure items {prec} top_bc={top_bc}: {dg['mu_pure_items']} (fields: {want}) of {dg['work_items']}")
     assert 0 < want < dg["work_items"]
     assert dg["mu_pure_items"] == want
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kw", [{"antitrapping": 0}, {"mu_frozen": 1}])
+def test_shortcuts_exact_without_antitrapping_or_with_frozen_mu(prec, kw):
+    """Without the anti-trapping current every FP64 item is light, and with
+    mu frozen no item may take a pure or light mu body: in both cases the
+    tile shortcuts still equal shortcuts off bitwise."""
+    shape = (96, 24, 70)
+    p = pfinputs.p0_params(solid_height=10)
+    p.update(kw)
+    p["dt"] = oracle.default_dt(p, shape)
+    a, da = _run(shape, p, prec, 10, 1, (4, 7, 10))
+    b, _ = _run(shape, p, prec, 10, 0, (4, 7, 10))
+    log(f"{prec} {kw}: fixed {da['fixed_items']}, light {da['light_items']}, "
+        f"pure {da['mu_pure_items']} of {da['work_items']}")
+    assert da["fixed_items"] > 0
+    if kw.get("mu_frozen"):
+        assert da["mu_pure_items"] == 0 and da["light_items"] == 0
+    else:
+        assert da["mu_pure_items"] > 0
+        if prec == "fp64":
+            assert da["light_items"] == da["work_items"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
