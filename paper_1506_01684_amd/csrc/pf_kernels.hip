@@ -27,12 +27,16 @@ namespace pfk {
 // FP64, rounds them to R, records the source copy, then advances the step
 // counter and the parity.  A domain whose step budget is spent is marked
 // inactive and left untouched.
+// z chunks whose fixed-point masks the prologue reduces in LDS.
+constexpr int kPrologueChunks = 1024;
+
 template <typename R>
 __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, int ndom) {
   DevDomain& d = *doms[blockIdx.x];
   __shared__ int64_t s_step;
   __shared__ int s_src, s_act;
   __shared__ double s_red[256];
+  __shared__ int s_chunk[kPrologueChunks];  // fixed-point mask of each z chunk
   if (threadIdx.x == 0) {
     int act = d.steps_left != 0;
     s_act = act;
@@ -86,6 +90,9 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
   const int64_t n = s_step;
   const double t0 = (double)n * d.dt, t1 = (double)(n + 1) * d.dt;
   PlaneCoef<R>* tab = static_cast<PlaneCoef<R>*>(d.coef);
+  const bool lds_chunks = d.nzc <= kPrologueChunks;  // else global atomics below
+  for (int i = threadIdx.x; i < kPrologueChunks; i += blockDim.x) s_chunk[i] = ~0;
+  __syncthreads();
   for (int k = threadIdx.x; k < d.nz; k += blockDim.x) {
     const double zc = (double)k * d.dx + zoff;
     const double Tn = d.T0 + d.G * (zc - d.v * t0);
@@ -154,11 +161,16 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     }
     c.chunk_fixed = ~0;
     tab[k] = c;
+    if (lds_chunks) atomicAnd(&s_chunk[k / d.zc], c.pure_fixed);
   }
   __syncthreads();
   // the fixed points of every plane of each z chunk, at its first plane
-  for (int k = threadIdx.x; k < d.nz; k += blockDim.x)
-    atomicAnd(&tab[k / d.zc * d.zc].chunk_fixed, tab[k].pure_fixed);
+  if (lds_chunks) {
+    for (int iz = threadIdx.x; iz < d.nzc; iz += blockDim.x) tab[iz * d.zc].chunk_fixed = s_chunk[iz];
+  } else {
+    for (int k = threadIdx.x; k < d.nz; k += blockDim.x)
+      atomicAnd(&tab[k / d.zc * d.zc].chunk_fixed, tab[k].pure_fixed);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     // the pure-phase flags of the copy this step writes are renewed by the
