@@ -155,10 +155,12 @@ typedef struct {
                            * exact); 0 with the shortcuts off, the direct
                            * variant, and before the first step           */
   int32_t mu_pure_items;  /* work items of the last step whose mu the tiled
-                           * sweep evaluated from mu alone: the phi-sweep
-                           * kept them and all their neighbours unchanged in
-                           * one pure phase, so phi^n = phi^{n+1} = e_a on
-                           * every cell read (exact); 0 when fixed_items is */
+                           * sweep evaluated from mu alone: they and every
+                           * cell their stencils read held one pure phase
+                           * before and after the phi-sweep, so phi^n =
+                           * phi^{n+1} = e_a there (Sec. 3.3 bulk shortcut,
+                           * exact); 0 with the shortcuts off, mu frozen,
+                           * the direct variant, and before the first step */
 } pf_diag;
 
 /* Device bytes a domain needs (both field copies, each with one extra
