@@ -39,8 +39,9 @@ def _sample_cells(shape, solid_height, rng, n_random=600):
     return sorted(cells)
 
 
-def _oracle_samples(p, phi0, mu0, cells):
-    """phi^{n+1} and mu^{n+1} of the sampled cells, one cell at a time."""
+def _oracle_samples(p, phi0, mu0, cells, t0=0.0):
+    """phi^{n+1} and mu^{n+1} of the sampled cells, one cell at a time, for
+    the step that starts at time t0."""
     nz, ny, nx = phi0.shape[1:]
     dt = p["dt"]
     phi1 = phi0.copy()
@@ -52,11 +53,11 @@ def _oracle_samples(p, phi0, mu0, cells):
             if 0 <= kk < nz:
                 need.add(((i + a) % nx, (j + b) % ny, kk))
     for (i, j, k) in need:
-        phi1[:, k, j, i] = oracle.phi_cell(p, phi0, mu0, 0.0, i, j, k)
+        phi1[:, k, j, i] = oracle.phi_cell(p, phi0, mu0, t0, i, j, k)
     out_phi, out_mu = [], []
     for (i, j, k) in cells:
         out_phi.append(phi1[:, k, j, i].copy())
-        out_mu.append(oracle.mu_cell(p, phi0, phi1, mu0, 0.0, dt, i, j, k))
+        out_mu.append(oracle.mu_cell(p, phi0, phi1, mu0, t0, t0 + dt, i, j, k))
     return np.array(out_phi), np.array(out_mu)
 
 
@@ -97,6 +98,47 @@ def test_c2_fullsize_one_step_fp64_sampled():
 
 def test_c3_fullsize_one_step_fp32_sampled():
     _one_step_sampled("c3", 5e-6, 1e-4)
+
+
+def test_c2_fullsize_step_with_tile_shortcuts_sampled():
+    """A later step of the 256x256x512 FP64 domain, when the bulk phi chunks
+    and the pure mu items are in use: the state before the step is read back
+    and the oracle evaluates the step's sampled cells from it (the liquid
+    far above the front, where those shortcuts act, included)."""
+    pf = lib()
+    pf.set_variant(1)
+    w = pfinputs.workload("c2")
+    shape = w["shape"]
+    p = pfinputs.with_dt(w["params"], oracle.default_dt(w["params"], shape))
+    d = pf.Domain(shape, w["prec"])
+    d.set_params(p)
+    d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
+    n = 5
+    d.step(n)
+    phi0, mu0 = d.read()
+    d.step(1)
+    phi_g, mu_g = d.read()
+    dg = d.diagnostics()
+    d.close()
+    log(f"c2 step {n + 1}: kept {dg['fixed_items']}, pure mu {dg['mu_pure_items']}, "
+        f"light {dg['light_items']} of {dg['work_items']}")
+    assert dg["fixed_items"] > dg["work_items"] // 2 and dg["mu_pure_items"] > dg["work_items"] // 2
+    rng = np.random.default_rng(11)
+    cells = _sample_cells(shape, w["solid_height"], rng)
+    nz, ny, nx = shape
+    for _ in range(200):  # the pure liquid far above the front
+        cells.append((int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz // 2, nz))))
+    cells = sorted(set(cells))
+    ph_o, mu_o = _oracle_samples(p, phi0, mu0, cells, t0=n * p["dt"])
+    idx = tuple(np.array(cells).T)
+    ph_g = np.stack([phi_g[a][idx[2], idx[1], idx[0]] for a in range(4)], axis=1)
+    mu_gs = np.stack([mu_g[q][idx[2], idx[1], idx[0]] for q in range(2)], axis=1)
+    e_phi = float(np.max(np.abs(ph_g - ph_o)))
+    scale = max(float(np.max(np.abs(mu_o))), 1e-300)
+    e_mu = float(np.max(np.abs(mu_gs - mu_o))) / scale
+    log(f"c2 step {n + 1} on {len(cells)} cells: phi max-abs {e_phi:.2e}, mu rel {e_mu:.2e}")
+    assert e_phi <= 1e-12 and e_mu <= 1e-12
+    assert float(np.max(np.abs(mu_gs - np.stack([mu0[q][idx[2], idx[1], idx[0]] for q in range(2)], 1)))) > 0
 
 
 def test_c2_fullsize_invariants_over_200_steps():
