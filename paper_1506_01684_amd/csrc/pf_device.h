@@ -100,7 +100,6 @@ struct PlaneCoef {
   // for the mu-sweep of cells whose phi^n, phi^{n+1} and neighbours are all
   // e_a, computed by the same functions as in the general face and cell
   // stages (mu_face_m, mu_cell_h, mu_cell_chi), so bitwise the same values:
-  R cdl[NP][NM];        // cbar_ai - cbar_li, rounded as in mu_cell
   R Mp[NP][NM];         // mu_face_m at pb = e_a, x/y faces
   R MpZ[NP][NM];        // mu_face_m at pb = e_a, z face
   R rchip[NP][NM];      // rcp_ of mu_cell's chi sum at phi^{n+1} = e_a

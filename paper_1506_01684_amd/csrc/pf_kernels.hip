@@ -129,7 +129,6 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
       }
     // coefficients of the mu-sweep of pure items (mu_pure_item)
     for (int a = 0; a < NP; ++a) {
-      for (int q = 0; q < NM; ++q) c.cdl[a][q] = c.cbar[a][q] - c.cbar[LQ][q];
       R e[NP], h[NP];
       for (int b = 0; b < NP; ++b) e[b] = b == a ? R(1) : R(0);
       mu_cell_h<R>(e, h);
