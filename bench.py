@@ -16,11 +16,19 @@ oracle timed on a bounded sample of the headline workload on the host's
 cores.
 
 Prints one JSON line.  MLUP/s = cells * steps / seconds / 1e6 (the paper's
-unit, Sec. 5).  Roofline: algorithmic bytes of the dominant kernel per
-launch (phi-sweep reads phi, mu and writes phi: 10 values per cell;
-mu-sweep reads phi^n, phi^{n+1}, mu and writes mu: 12 values per cell)
-divided by its average HIP-event duration, against 8 TB/s; "traffic" is the
-HBM bytes per launch that rocprofv3 counted for the same kernel sources.
+unit, Sec. 5).  Roofline: the bytes the dominant sweep owes per launch,
+divided by its average HIP-event duration, against 8 TB/s.  What a sweep
+owes follows from the work it does: an item the phi-sweep evaluates reads
+phi^n and mu^n and writes phi^{n+1} (10 values per cell), an item the bulk
+shortcut keeps owes nothing, or 8 values per cell when it has to be copied;
+an item the mu-sweep evaluates in full reads phi^n, phi^{n+1}, mu^n and
+writes mu^{n+1} (12 values per cell), a pure item reads mu^n and writes
+mu^{n+1} (4 values).  With the shortcuts off every item is evaluated, so the
+owed bytes are the dense ones.  The item counts come from the library's
+diagnostics (the step before and the last step of the timed run,
+averaged).  The dense bytes over the same time are reported beside it as
+"effective_gbs".  "traffic" is the HBM bytes per launch that rocprofv3
+counted for the same kernel sources.
 """
 from __future__ import annotations
 
@@ -64,6 +72,7 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int
          f"dt={d.dt:.6g} warmup {warmup}")
     d.step(warmup)
     d.sync()
+    before = d.diagnostics()
     torch.cuda.synchronize()
     _log(f"[bench] {workload}: timing {steps} steps")
     t0 = time.perf_counter()
@@ -81,13 +90,73 @@ def run_gpu(workload: str, steps: int, warmup: int, variant: int, shortcuts: int
         "nonfinite": diag["nonfinite"], "max_simplex_dev": diag["max_simplex_dev"],
         "window_shifts": diag["window_shifts"],
     }
+    owed = owed_bytes(before, diag, cells, esize, shortcuts, variant)
+    out["items"] = owed["items"]
     for k in ("phi", "mu"):
-        bytes_launch = VALUES_PER_CELL[k] * esize * cells
-        gbs = bytes_launch / (out[f"{k}_ms"] * 1e-3) / 1e9
-        out[f"{k}_gbs"] = gbs
-        out[f"{k}_bytes_per_launch"] = bytes_launch
-    step_bytes = (VALUES_PER_CELL["phi"] + VALUES_PER_CELL["mu"]) * esize * cells
-    out["step_hbm_frac"] = step_bytes / (wall / steps) / 1e9 / HBM_PEAK_GBS
+        dense = VALUES_PER_CELL[k] * esize * cells
+        sec = out[f"{k}_ms"] * 1e-3
+        out[f"{k}_bytes_per_launch"] = owed[k]
+        out[f"{k}_gbs"] = owed[k] / sec / 1e9
+        out[f"{k}_dense_bytes"] = dense
+        out[f"{k}_effective_gbs"] = dense / sec / 1e9
+    step_dense = (VALUES_PER_CELL["phi"] + VALUES_PER_CELL["mu"]) * esize * cells
+    step_s = wall / steps
+    out["step_hbm_frac"] = (owed["phi"] + owed["mu"]) / step_s / 1e9 / HBM_PEAK_GBS
+    out["step_effective_hbm_frac"] = step_dense / step_s / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+def owed_bytes(before: dict, after: dict, cells: int, esize: int, shortcuts: int,
+               variant: int) -> dict:
+    """Bytes each sweep owes per step from the work it does (see the module
+    docstring), from the item counts of the library's diagnostics: the mean
+    of the step before the timed run and its last step.  Items are counted
+    at the mean cells per item (every item of the benchmark's domains is
+    whole)."""
+    items = after["work_items"]
+    cpi = cells / items
+
+    def mean(k):
+        return 0.5 * (before[k] + after[k])
+
+    if shortcuts and variant == 1:
+        fixed, copied, pure = mean("fixed_items"), mean("copied_items"), mean("mu_pure_items")
+    else:
+        fixed = copied = pure = 0.0
+    phi = ((items - fixed) * VALUES_PER_CELL["phi"] + copied * 8) * cpi * esize
+    mu = ((items - pure) * VALUES_PER_CELL["mu"] + pure * 4) * cpi * esize
+    return {"phi": phi, "mu": mu,
+            "items": {"work": items, "fixed": fixed, "copied": copied, "mu_pure": pure,
+                      "light": mean("light_items")}}
+
+
+def sweep_kernels(sweep: str, real: str, aniso: bool) -> str:
+    """Kernel names of one sweep as rocprofv3 lists them, joined by '+'.  The
+    mu-sweep is two launches (FP64: pure and light items, then the rest;
+    FP32: pure items, then the rest), the phi-sweep the bulk shortcut's
+    launch and the tiled sweep; with the shortcuts off the first launch of
+    each sweep finds no item and returns at once."""
+    if sweep == "mu":
+        return "mu_light_f64+mu_tiled_f64" if real == "double" else "mu_pure_f32+mu_tiled_f32"
+    return (f"phi_bulk_kernel<{real}>+phi_tiled_f{64 if real == 'double' else 32}"
+            f"{'_aniso' if aniso else ''}")
+
+
+def sweep_rooflines(run: dict, real: str, aniso: bool, workload: str, variant: int,
+                    plain: bool = False) -> dict:
+    """Per-sweep roofline of one timed run: the bytes the sweep owes per
+    launch over its HIP-event time, against the HBM peak; the counter bytes
+    of the same kernels when a matching rocprofv3 record exists."""
+    out = {}
+    for k in ("phi", "mu"):
+        kn = sweep_kernels(k, real, aniso)
+        tr = recorded_traffic(kn, workload + ("_plain" if plain else "")) if variant == 1 else None
+        out[k] = {"kernel": kn, "ms": round(run[f"{k}_ms"], 4),
+                  "bytes_per_launch": round(run[f"{k}_bytes_per_launch"]),
+                  "achieved": round(run[f"{k}_gbs"], 1),
+                  "frac": round(run[f"{k}_gbs"] / HBM_PEAK_GBS, 4),
+                  "effective_gbs": round(run[f"{k}_effective_gbs"], 1),
+                  "traffic": None if tr is None else round(tr)}
     return out
 
 
@@ -280,10 +349,22 @@ def recorded_traffic(kernel: str, workload: str):
     return total
 
 
+def fp32_error(p32, m32, p64, m64) -> tuple[float, float]:
+    """FP32 result against its FP64 twin: max-abs error of phi and, per mu
+    component, max|dmu| / max|mu| (the larger of the two)."""
+    import numpy as np
+
+    dphi = float(np.max(np.abs(p32 - p64)))
+    dmu = max(float(np.max(np.abs(m32[q] - m64[q]))) / max(float(np.max(np.abs(m64[q]))), 1e-300)
+              for q in range(2))
+    return dphi, dmu
+
+
 def run_pack(count: int, steps: int, warmup: int) -> dict:
     """64 uneven FP32 domains: one pack (one launch per kernel per step over
     all domains, step captured in a HIP graph) vs looping single-domain
-    launches over the same domains."""
+    launches over the same domains; then the same domains as an FP64 pack,
+    whose results give the FP32 pack's error."""
     import torch
 
     import paper_1506_01684_amd as pf
@@ -292,29 +373,41 @@ def run_pack(count: int, steps: int, warmup: int) -> dict:
     ws = pfinputs.pack_workloads(count)
     cells = sum(w["shape"][0] * w["shape"][1] * w["shape"][2] for w in ws)
 
-    def make():
+    def make(prec="fp32"):
         doms = []
         for w in ws:
-            d = pf.Domain(w["shape"], w["prec"])
+            d = pf.Domain(w["shape"], prec)
             d.set_params(w["params"])
             d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
             doms.append(d)
         return doms
 
-    doms = make()
-    pk = pf.Pack("fp32", max_domains=count)
-    for d in doms:
-        pk.add(d, warmup + steps)
-    pk.step(warmup)
-    pk.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pk.step(steps)
-    pk.sync()
-    t_pack = time.perf_counter() - t0
-    pk.close()
-    for d in doms:
-        d.close()
+    def packed(prec):
+        doms = make(prec)
+        pk = pf.Pack(prec, max_domains=count)
+        for d in doms:
+            pk.add(d, warmup + steps)
+        pk.step(warmup)
+        pk.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pk.step(steps)
+        pk.sync()
+        t = time.perf_counter() - t0
+        return pk, doms, t
+
+    pk32, doms32, t_pack = packed("fp32")
+    _log("[bench] pack: FP64 twin")
+    pk64, doms64, t_pack64 = packed("fp64")
+    dphi = dmu = 0.0
+    for a, b in zip(doms32, doms64):
+        e = fp32_error(*a.read(), *b.read())
+        dphi, dmu = max(dphi, e[0]), max(dmu, e[1])
+    for pk, doms in ((pk32, doms32), (pk64, doms64)):
+        pk.close()
+        for d in doms:
+            d.close()
+    _log("[bench] pack: looped single-domain launches")
     doms = make()
     for d in doms:
         d.step(warmup)
@@ -334,27 +427,38 @@ def run_pack(count: int, steps: int, warmup: int) -> dict:
         "steps": steps, "pack_mlups": round(cells * steps / t_pack / 1e6, 1),
         "loop_mlups": round(cells * steps / t_loop / 1e6, 1),
         "speedup": round(t_loop / t_pack, 3),
+        "fp64_pack_mlups": round(cells * steps / t_pack64 / 1e6, 1),
+        "error_vs_fp64": {"steps": warmup + steps, "phi_max_abs": dphi, "mu_rel": dmu,
+                          "tolerance": {"phi_max_abs": 2e-4, "mu_rel": 1e-4},
+                          "within": bool(dphi <= 2e-4 and dmu <= 1e-4)},
     }
 
 
 def run_serving(count: int, lateral, steps_rng, rate: float, budget: float, serial: bool,
-                policies=("fifo", "sjf"), progress: bool = False) -> dict:
+                policies=("fifo", "sjf"), progress: bool = False, fp32_twins: int = 0) -> dict:
     """Poisson arrivals of Voronoi solves of mixed size, step count and
     precision through the continuous-batching server; the serial baseline
     runs the same trace first come, first served with single-domain
-    launches."""
+    launches.  For the `fp32_twins` smallest FP32 requests the server keeps
+    the fields (read back when the request finishes), and each is solved
+    again in FP64 afterwards for the FP32 error."""
     import pfinputs
     from paper_1506_01684_amd import serving as S
 
     trace = pfinputs.serving_trace(count=count, rate=rate, lateral=lateral, steps=steps_rng)
-    reqs = [S.request_from_trace(t) for t in trace]
+    twins = sorted((t for t in trace if t["prec"] == "fp32"),
+                   key=lambda t: t["shape"][0] * t["shape"][1] * t["shape"][2])[:fp32_twins]
+    twin_ids = {t["id"] for t in twins}
     out = {
         "workload": f"{count} requests, Poisson {rate}/s, lateral {lateral[0]}-{lateral[1]}, "
                     f"Nz = 2L, steps {steps_rng[0]}-{steps_rng[1]}, fp32/fp64 half each, "
                     f"budget {budget / 1e9:.0f} GB",
+        "lups": sum(t["shape"][0] * t["shape"][1] * t["shape"][2] * t["steps"] for t in trace),
     }
+    kept = {}
     for pol in policies:
         _log(f"[bench] serving with policy {pol}")
+        reqs = [S.request_from_trace(t, keep_fields=t["id"] in twin_ids) for t in trace]
         be = S.GpuBackend(max_domains=256)
         kw = {} if pol == "fifo" else dict(policy="sjf", target_cells=32e6, rate=2e10)
         srv = S.Server(be, budget_bytes=budget, max_slots=256, round_steps=25,
@@ -367,8 +471,32 @@ def run_serving(count: int, lateral, steps_rng, rate: float, budget: float, seri
         else:
             out["server_sjf"] = dict(S.summarize(res), policy="shortest expected job first "
                                                               "with aging, packs held to 32M cells")
+        for r in res:
+            if r.id in twin_ids and r.fields is not None:
+                kept[r.id] = r.fields
     if serial:
-        out["serial_fifo"] = S.summarize(S.run_serial_gpu(reqs))
+        _log("[bench] serving: serial FIFO")
+        out["serial_fifo"] = S.summarize(S.run_serial_gpu(
+            [S.request_from_trace(t) for t in trace]))
+    if twins:
+        import paper_1506_01684_amd as pf
+
+        errs = []
+        for t in twins:
+            if t["id"] not in kept:
+                continue
+            d = pf.Domain(t["shape"], "fp64")
+            d.set_params(t["params"])
+            d.init_voronoi(t["seed"], t["nseeds"], t["solid_height"])
+            d.step(t["steps"])
+            e = fp32_error(*kept[t["id"]], *d.read())
+            d.close()
+            errs.append({"id": t["id"], "shape": list(t["shape"]), "steps": t["steps"],
+                         "phi_max_abs": e[0], "mu_rel": e[1],
+                         "within": bool(e[0] <= 2e-4 and e[1] <= 1e-4)})
+        out["fp32_error_vs_fp64"] = {
+            "note": f"the {len(errs)} smallest FP32 requests, solved again in FP64 alone",
+            "requests": errs, "tolerance": {"phi_max_abs": 2e-4, "mu_rel": 1e-4}}
     return out
 
 
@@ -432,8 +560,8 @@ def main():
                     help="skip the interface/solid/liquid timings of the headline domain")
     ap.add_argument("--no-output", action="store_true",
                     help="skip the mesh and checkpoint timings of the headline domain")
-    ap.add_argument("--pack-steps", type=int, default=100)
-    ap.add_argument("--serve-count", type=int, default=64)
+    ap.add_argument("--pack-steps", type=int, default=500)
+    ap.add_argument("--serve-count", type=int, default=24)
     ap.add_argument("--full-serving", action="store_true",
                     help="only run the full serving trace: 128 requests, lateral 64-384, "
                          "steps 200-5000, 200 GB budget (long)")
@@ -470,12 +598,7 @@ def main():
     achieved = main_run[f"{dom}_gbs"]
     real = "double" if main_run["prec"] == "fp64" else "float"
     aniso = "true" if args.workload == "c3" else "false"
-    # the mu-sweep is two launches (FP64: pure and light items, then the
-    # rest; FP32: pure items, then the rest); the roofline covers the sweep
-    kname = (("mu_light_f64+mu_tiled_f64" if real == "double" else "mu_pure_f32+mu_tiled_f32")
-             if dom == "mu"
-             else f"phi_bulk_kernel<{real}>+phi_tiled_f{64 if real == 'double' else 32}"
-                  f"{'_aniso' if aniso == 'true' else ''}")
+    kname = sweep_kernels(dom, real, aniso == "true")
     traffic = recorded_traffic(kname, args.workload) if args.variant == 1 else None
     line = {
         "metric": "MLUP/s of phi+mu step (FP32 vs FP64) + %HBM peak",
@@ -494,19 +617,22 @@ def main():
             "workload": f"{args.workload}: {'x'.join(map(str, main_run['shape']))} cells, "
                         f"{main_run['prec']}, N=4 phases, K-1=2 mu",
             "cells": main_run["cells"], "variant": args.variant, "shortcuts": args.shortcuts,
+            # bytes the two sweeps owe for the work they do, per step time
             "hbm_frac_step": round(main_run["step_hbm_frac"], 4),
+            # dense bytes (22 values per cell) per step time
+            "effective_hbm_frac_step": round(main_run["step_effective_hbm_frac"], 4),
             "phi_sweep_ms": round(main_run["phi_ms"], 4), "mu_sweep_ms": round(main_run["mu_ms"], 4),
-            # algorithmic bytes per sweep over its time; the phi-sweep's bulk
-            # shortcut moves fewer bytes than that (chunks kept unchanged)
-            "phi_sweep_alg_gbs": round(main_run["phi_gbs"], 1),
-            "mu_sweep_alg_gbs": round(main_run["mu_gbs"], 1),
+            "items": main_run["items"],
         },
         "roofline": {
             "bound": "hbm", "kernel": kname,
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
-            "bytes_per_launch": main_run[f"{dom}_bytes_per_launch"],
+            "bytes_per_launch": round(main_run[f"{dom}_bytes_per_launch"]),
+            "effective_gbs": round(main_run[f"{dom}_effective_gbs"], 1),
+            "dense_bytes_per_launch": main_run[f"{dom}_dense_bytes"],
+            "sweeps": sweep_rooflines(main_run, real, aniso == "true", args.workload, args.variant),
         },
     }
     if not args.no_plain and args.shortcuts == 1:
@@ -516,6 +642,9 @@ def main():
                     "results are bitwise identical)",
             "mlups": round(rp["mlups"], 1), "ms_per_step": round(rp["ms_per_step"], 4),
             "phi_sweep_ms": round(rp["phi_ms"], 4), "mu_sweep_ms": round(rp["mu_ms"], 4),
+            "hbm_frac_step": round(rp["step_hbm_frac"], 4),
+            "roofline": sweep_rooflines(rp, real, aniso == "true", args.workload, args.variant,
+                                        plain=True),
         }
     stream = run_stream()
     best = max(stream["copy_gbs"], stream["add_gbs"])
@@ -536,13 +665,20 @@ def main():
             "workload": "c3: 512x512x1024 cells, fp32 bulk, cubic anisotropy 0.05",
             "mlups": round(r32["mlups"], 1), "ms_per_step": round(r32["ms_per_step"], 4),
             "hbm_frac_step": round(r32["step_hbm_frac"], 4),
+            "effective_hbm_frac_step": round(r32["step_effective_hbm_frac"], 4),
             "phi_sweep_ms": round(r32["phi_ms"], 4), "mu_sweep_ms": round(r32["mu_ms"], 4),
-            "phi_sweep_alg_gbs": round(r32["phi_gbs"], 1), "mu_sweep_alg_gbs": round(r32["mu_gbs"], 1),
+            "items": r32["items"],
+            "roofline": sweep_rooflines(r32, "float", True, "c3", args.variant),
             "steps": args.fp32_steps,
         }
         if not args.no_plain and args.shortcuts == 1:
             rp = run_gpu("c3", args.fp32_steps, 5, args.variant, shortcuts=0)
-            line["fp32"]["plain_mlups"] = round(rp["mlups"], 1)
+            line["fp32"]["plain"] = {
+                "mlups": round(rp["mlups"], 1), "ms_per_step": round(rp["ms_per_step"], 4),
+                "hbm_frac_step": round(rp["step_hbm_frac"], 4),
+                "phi_sweep_ms": round(rp["phi_ms"], 4), "mu_sweep_ms": round(rp["mu_ms"], 4),
+                "roofline": sweep_rooflines(rp, "float", True, "c3", args.variant, plain=True),
+            }
         if not args.no_fp32_error:
             line["fp32"]["error_vs_fp64"] = run_fp32_error(1000)
     if not args.no_pack and args.workload == "c2":
@@ -550,8 +686,8 @@ def main():
         line["pack"] = run_pack(64, args.pack_steps, 5)
     if not args.no_serve and args.workload == "c2":
         _log("[bench] serving trace")
-        line["serving"] = run_serving(args.serve_count, (64, 160), (200, 1000), 20.0, 200e9,
-                                      serial=True)
+        line["serving"] = run_serving(args.serve_count, (64, 384), (200, 5000), 20.0, 200e9,
+                                      serial=True, fp32_twins=3)
     if not args.no_cpu:
         _log("[bench] timing the CPU oracle")
         line["cpu_baseline"] = run_cpu_baseline(args.workload)

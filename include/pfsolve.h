@@ -161,20 +161,35 @@ typedef struct {
                            * phi^{n+1} = e_a there (Sec. 3.3 bulk shortcut,
                            * exact); 0 with the shortcuts off, mu frozen,
                            * the direct variant, and before the first step */
+  int32_t copied_items;   /* of the fixed_items, those whose phi the sweep
+                           * had to copy into the copy it writes (the others
+                           * were kept in both copies the step before) */
+  int32_t reserved;       /* 0 */
 } pf_diag;
 
 /* Device bytes a domain needs (both field copies, each with one extra
- * plane per field for the Dirichlet ghost, plus scratch). */
+ * plane per field for the Dirichlet ghost, plus scratch).  Not in the
+ * paper: the memory budget of the serving loop (admission against HBM)
+ * needs it.  The two copies are Algorithm 1's source and destination
+ * fields; the layout is structure of arrays, x fastest, rows padded to
+ * 128 bytes.  INVALID_ARG for sizes <= 0 or a total that overflows. */
 pf_status pf_required_bytes(const pf_domain_desc* desc, size_t* out);
 
-/* Create a domain on the current HIP device.  borrowed: NULL = allocate.
- * stream: a hipStream_t (NULL = null stream).  Errors: INVALID_ARG for
- * sizes <= 0 or overflowing, OOM, DEVICE. */
+/* Create a domain on the current HIP device: the regular grid of
+ * equidistant cells of Sec. 2 (Sec. 3.1, block structure, with one block
+ * per domain here).  Not in the paper as a call: the library's own
+ * lifetime management.  borrowed: NULL = allocate, else a caller-owned
+ * device buffer of at least pf_required_bytes() that must outlive the
+ * domain.  stream: a hipStream_t (NULL = null stream).  Errors:
+ * INVALID_ARG for sizes <= 0 or overflowing, OOM, DEVICE. */
 pf_status pf_create_domain(const pf_domain_desc* desc,
                            const pf_device_buffer* borrowed, void* stream,
                            pf_domain** out);
 
-/* Copy and validate parameters; resolve dt.  Errors: INVALID_ARG for
+/* Copy and validate parameters; resolve dt (the model parameters of
+ * Sec. 2 and the explicit Euler step of Algorithm 1).  Errors: STATE for a
+ * pack member (its descriptor belongs to the pack's captured step);
+ * INVALID_ARG for
  * non-positive eps/tau/dx, chi <= 0 over the domain's temperature range,
  * negative gamma or D, delta outside [0, 1/15); UNSTABLE for an explicit dt
  * above the stability bound min(dt_phi, dt_mu) with
@@ -186,7 +201,7 @@ pf_status pf_set_params(pf_domain* d, const pf_params* p);
 pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
 
 /* Initialise both sweeps' source fields; resets the step index and the
- * window shift count to 0.
+ * window shift count to 0.  STATE for a pack member.
  * VORONOI (Sec. 2.1): nseeds points drawn with SplitMix64 (Steele, Lea,
  * Flood 2014) as (u nx, u ny), u = (next >> 11) 2^-53, x first; seed s gets
  * solid phase s mod 3; each column takes the nearest seed by periodic
@@ -195,7 +210,10 @@ pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
  * HOST: copy (and for FP32 round) the caller's arrays.  Synchronises. */
 pf_status pf_init_fields(pf_domain* d, const pf_init* init);
 
-/* Resume from a checkpoint: the next step is number `step`, t = step dt.
+/* Resume from a checkpoint (Sec. 3.2 checkpointing): the next step is
+ * number `step`, t = step dt (times are products, as the frozen
+ * temperature of Sec. 2 is a function of t).  STATE before the fields are
+ * set or for a pack member; INVALID_ARG for step < 0.
  * The window shift count is kept; a caller resuming a windowed run from
  * host fields sets pf_params.zoff to the old zoff plus shifts * dx. */
 pf_status pf_set_time(pf_domain* d, int64_t step);
@@ -211,7 +229,10 @@ pf_status pf_step(pf_domain* d, int64_t n);
 pf_status pf_step_timed(pf_domain* d, int64_t n, double* phi_ms,
                         double* mu_ms);
 
-/* Wait for all enqueued work; report asynchronous errors. */
+/* Wait for all enqueued work; report asynchronous errors.  Not in the
+ * paper: the stream model of this library (every call enqueues on the
+ * domain's HIP stream).  Reports NONFINITE when in-loop diagnostics found
+ * a non-finite cell, DEVICE for a HIP error. */
 pf_status pf_sync(pf_domain* d);
 
 /* Copy the current state to host (FP32 widened to FP64) and/or compute the
@@ -220,10 +241,14 @@ pf_status pf_sync(pf_domain* d);
  * non-finite cell. */
 pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag);
 
-/* Number of completed steps of the current state. */
+/* Number of completed steps of the current state: the time level n of
+ * Algorithm 1's source fields (t = n dt).  Synchronises with the device's
+ * step counter. */
 pf_status pf_get_step(const pf_domain* d, int64_t* step);
 
-/* Synchronise and free owned memory.  NULL is accepted. */
+/* Synchronise and free owned memory (a borrowed buffer is left to its
+ * owner); a pack member is removed from its pack first.  NULL is accepted.
+ * Not in the paper: the library's own lifetime management. */
 void pf_destroy(pf_domain* d);
 
 /* ------------------------------------------------------------ output path
@@ -271,7 +296,10 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path);
 pf_status pf_mesh_phase(pf_domain* d, int32_t phase, double iso, const pf_device_buffer* out,
                         int64_t* ntri);
 
-/* Batched stepping (many independent domains of one precision).  Each pack
+/* Batched stepping (many independent domains of one precision).  Not in
+ * the paper, which runs one large domain over many processes: batching
+ * and serving of many independent solves are this library's use of one
+ * GPU; each member still takes exactly the steps of Algorithm 1.  Each pack
  * step runs the per-plane coefficient kernel, the phi-sweep and the
  * mu-sweep once each for all member domains, over a flattened list of
  * (domain, tile) items; the step is captured once in a HIP graph and
@@ -290,10 +318,12 @@ pf_status pf_pack_remove(pf_pack* pk, pf_domain* d);
 pf_status pf_pack_sync(pf_pack* pk);
 void pf_pack_destroy(pf_pack* pk);
 
-/* Kernel variant used by subsequent sweeps of every domain: 0 = one thread
- * per cell evaluating all six faces ("direct"), 1 = z-marching tiles that
- * evaluate every face once and share it (default).  Both compute the same
- * model; the tests hold both to the same tolerance. */
+/* Kernel variant used by subsequent sweeps of every domain (Algorithm 1's
+ * two kernels, in two implementations; not in the paper as a call):
+ * 0 = one thread per cell evaluating all six faces ("direct"), 1 = z-marching
+ * tiles that evaluate every face once and share it (default; Sec. 3.3,
+ * staggered-value buffering).  Both compute the same model; the tests hold
+ * both to the same tolerance.  INVALID_ARG for any other value. */
 pf_status pf_set_variant(int32_t variant);
 
 const char* pf_last_error(void);

@@ -262,6 +262,7 @@ class Domain:
             "window_shifts": dg.window_shifts,
             "light_items": dg.light_items, "work_items": dg.work_items,
             "fixed_items": dg.fixed_items, "mu_pure_items": dg.mu_pure_items,
+            "copied_items": dg.copied_items,
         }
 
 

@@ -66,6 +66,8 @@ class PfDiag(C.Structure):
         ("work_items", C.c_int32),
         ("fixed_items", C.c_int32),
         ("mu_pure_items", C.c_int32),
+        ("copied_items", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

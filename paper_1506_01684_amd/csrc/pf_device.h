@@ -41,11 +41,13 @@ constexpr int NFIELD = 6;  // phi_0..phi_3, mu_0, mu_1 in one copy
 
 // Per-step counts of the tiled sweeps, after the item words of jfree: the
 // light items (no anti-trapping face), the items the phi bulk shortcut
-// keeps, and the items whose mu-sweep reads mu alone.  Increments of one
-// address are serialised, so each count is spread over kCountSlots words
-// on 128-byte lines of their own (the work item's number picks the slot).
-constexpr int kCountKinds = 3, kCountSlots = 8, kCountStride = 32;  // stride in words
-constexpr int kCountLight = 0, kCountFixed = 1, kCountPure = 2;
+// keeps, the items whose mu-sweep reads mu alone, and the kept items whose
+// phi the bulk shortcut had to copy (not already in both copies).
+// Increments of one address are serialised, so each count is spread over
+// kCountSlots words on 128-byte lines of their own (the work item's number
+// picks the slot).
+constexpr int kCountKinds = 4, kCountSlots = 8, kCountStride = 32;  // stride in words
+constexpr int kCountLight = 0, kCountFixed = 1, kCountPure = 2, kCountCopied = 3;
 constexpr int kCountWords = kCountKinds * kCountSlots * kCountStride;
 __host__ __device__ inline int64_t count_base(int64_t nitems) {  // word offset in jfree
   return (nitems + kCountStride - 1) / kCountStride * kCountStride;

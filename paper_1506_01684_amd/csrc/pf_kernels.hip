@@ -136,13 +136,29 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
       mu_face_m<R, true>(c, e, c.MpZ[a]);
       for (int q = 0; q < NM; ++q) c.rchip[a][q] = rcp_(mu_cell_chi<R>(c, q, h));
     }
-    // A pure cell (phi = e_a) whose face terms vanish has rhs_a = 0 and
-    // rhs_b = (T/eps) 16/pi^2 gamma_ab, so after the Euler step
-    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m), m the mean.  The
-    // projection returns e_a exactly when every y_b stays below
-    // y_a - 1 = rate_a m; the margin covers FP32 rounding of y.
+    // A pure cell (phi = e_a) whose face terms vanish (A = 0) is a fixed
+    // point when the cell stage maps it to e_a exactly.  Decided by running
+    // that cell stage (phi_cell in the path's precision) on e_a with A = 0:
+    // its driving force is zero for every finite mu (h = e_a, so
+    // psi_a - sum h psi = 0 and phi_b = 0 multiplies the rest), so mu = 0
+    // stands for any state.  As a guard against a different fusion of the
+    // same arithmetic where the sweep inlines it, the step must also keep
+    // a clear margin: rhs_a = 0, rhs_b = (T/eps) 16/pi^2 gamma_ab, so
+    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m) (m the mean), and
+    // the projection returns e_a when every y_b stays below y_a - 1; the
+    // margin is relative, plus an absolute 2^-20 for the rounding of y_a
+    // near 1 in FP32.
     c.pure_fixed = 0;
     for (int a = 0; a < NP; ++a) {
+      R e[NP], A[NP], m0[NM] = {R(0), R(0)};
+      for (int b = 0; b < NP; ++b) {
+        e[b] = b == a ? R(1) : R(0);
+        A[b] = R(0);
+      }
+      double out[NP];
+      phi_cell<R>(kparams<R>(d), c, e, m0, A, out);
+      bool fixed = true;
+      for (int b = 0; b < NP; ++b) fixed = fixed && (R)out[b] == e[b];
       double rhs[NP], m = 0.0;
       for (int b = 0; b < NP; ++b) {
         rhs[b] = b == a ? 0.0 : (Tn / d.eps) * d.kp64.g16[a < b ? pair_index(a, b) : pair_index(b, a)];
@@ -150,11 +166,10 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
       }
       m *= 0.25;
       const double thr = d.kp64.rate[a] * m;
-      bool fixed = true;
       for (int b = 0; b < NP; ++b) {
         if (b == a) continue;
         const double yb = -d.kp64.rate[b] * (rhs[b] - m);
-        fixed = fixed && yb + 1e-5 * (fabs(thr) + fabs(yb)) < thr;
+        fixed = fixed && yb + 1e-5 * (fabs(thr) + fabs(yb)) + 0x1p-20 < thr;
       }
       if (fixed) c.pure_fixed |= 1 << a;
     }

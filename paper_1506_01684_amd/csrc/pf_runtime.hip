@@ -456,6 +456,8 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
 
 pf_status pf_set_params(pf_domain* d, const pf_params* p) {
   if (!d || !p) return fail(PF_ERR_INVALID_ARG, "null argument");
+  // a member's descriptor and step budget belong to its pack's captured step
+  if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
   if (p->diag_every < 0) return fail(PF_ERR_INVALID_ARG, "diag_every must be >= 0");
   if (p->window_z != 0 && (p->window_z < 1 || p->window_z > d->desc.nz - 2))
     return fail(PF_ERR_INVALID_ARG, "window_z must be 0 or in [1, nz-2]");
@@ -524,6 +526,7 @@ pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound) {
 
 pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   if (!d || !in) return fail(PF_ERR_INVALID_ARG, "null argument");
+  if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
   const pf_domain_desc& g = d->desc;
   const Layout& L = d->L;
   pf_status st;
@@ -589,6 +592,7 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
 pf_status pf_set_time(pf_domain* d, int64_t step) {
   pf_status st = check_state(d);
   if (st != PF_OK) return st;
+  if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
   if (step < 0) return fail(PF_ERR_INVALID_ARG, "step must be >= 0");
   DevDomain cur;
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
@@ -727,6 +731,8 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->light_items = (int32_t)counts[kCountLight];
     diag->fixed_items = (int32_t)counts[kCountFixed];
     diag->mu_pure_items = (int32_t)counts[kCountPure];
+    diag->copied_items = (int32_t)counts[kCountCopied];
+    diag->reserved = 0;
     diag->work_items = d->T.blocks();
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");

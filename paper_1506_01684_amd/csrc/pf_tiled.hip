@@ -765,6 +765,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
     const bool same =
         to_const(static_cast<const uint8_t*>(dd.pflag[dd.cur_src]))[chunk_index(dd, cid)] & kSame;
     if (!same) {
+      if (lane == 0) atomicAdd(X.jc + count_word(kCountCopied, X.slot), 1u);
 #pragma unroll 1
       for (int c = lane; c < kTileThreads; c += 64) {
         const TileGeo Gc = make_tile<R>(dd, X.local, c);

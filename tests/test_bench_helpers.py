@@ -41,3 +41,22 @@ def test_committed_summary_parses():
     rec = json.loads(text.split("```json\n", 1)[1].split("\n```", 1)[0])
     assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
     assert "c2" in rec["kernels"] and "c3" in rec["kernels"]
+
+
+def test_owed_bytes_follow_the_item_classes():
+    """Bytes a sweep owes per step: evaluated phi items 10 values per cell,
+    kept items nothing (8 values when copied); mu items 12 values per cell,
+    pure items 4.  With the shortcuts off (or the direct variant) every
+    item is evaluated."""
+    cells, es = 4096 * 8192, 8
+    d0 = {"work_items": 4096, "fixed_items": 2000, "copied_items": 10, "mu_pure_items": 2500,
+          "light_items": 3000}
+    d1 = dict(d0, fixed_items=2100, copied_items=0, mu_pure_items=2600)
+    o = bench.owed_bytes(d0, d1, cells, es, 1, 1)
+    cpi = 8192
+    assert o["phi"] == ((4096 - 2050) * 10 + 5 * 8) * cpi * es
+    assert o["mu"] == ((4096 - 2550) * 12 + 2550 * 4) * cpi * es
+    assert o["items"]["fixed"] == 2050 and o["items"]["mu_pure"] == 2550
+    for sc, var in ((0, 1), (1, 0)):
+        o = bench.owed_bytes(d0, d1, cells, es, sc, var)
+        assert o["phi"] == 10 * cells * es and o["mu"] == 12 * cells * es

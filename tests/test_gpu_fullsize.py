@@ -9,6 +9,8 @@ benchmark times (tiled variant, the runtime's own tiling):
   - the FP32 path against the GPU FP64 path after 1000 steps on the
     512x512x1024 domain (phi max-abs <= 2e-4, mu relative <= 1e-4).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -187,3 +189,51 @@ def test_c3_fp32_vs_fp64_after_1000_steps():
         f"sum c fp32 vs fp64 {drift}")
     assert dphi <= 2e-4 and dmu <= 1e-4
     assert g32["nonfinite"] == 0 and g64["nonfinite"] == 0
+
+
+GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_fp64_1000.npz")
+
+
+@pytest.mark.parametrize("shortcuts", [1, 0])
+def test_c2_1000_steps_fp64_against_oracle(shortcuts):
+    """The 256x256x512 FP64 workload over its 1000 steps against the
+    oracle's state after 1000 steps (tests/golden/c2_fp64_1000.npz, written
+    by tests/golden/make_c2_1000.py from the oracle alone): about 4900
+    sampled cells (whole columns, front columns, boundary planes, tile and
+    chunk edges, liquid and solid interiors) at rel-inf <= 1e-12 per field
+    (max error over the sample / max |value| of the whole field), and the
+    total concentration of the whole domain."""
+    from tests.golden.make_c2_1000 import params_digest
+
+    if not os.path.exists(GOLDEN_C2):
+        pytest.skip("tests/golden/c2_fp64_1000.npz has not been written")
+    z = np.load(GOLDEN_C2)
+    w = pfinputs.workload("c2")
+    assert str(z["params_sha256"]) == params_digest(w["params"])
+    steps = int(z["steps"])
+    p = pfinputs.with_dt(w["params"], float(z["dt"]))
+    pf = lib()
+    pf.set_variant(1)
+    log(f"case c2 {steps} steps FP64 shortcuts={shortcuts}")
+    d = pf.Domain(w["shape"], "fp64")
+    d.set_params(dict(p, shortcuts=shortcuts))
+    d.init_voronoi(w["seed"], w["nseeds"], w["solid_height"])
+    d.step(steps)
+    phi_g, mu_g = d.read()
+    dg = d.diagnostics()
+    d.close()
+    i, j, k = z["cells"][:, 0], z["cells"][:, 1], z["cells"][:, 2]
+    ph = np.stack([phi_g[a][k, j, i] for a in range(4)], axis=1)
+    mu = np.stack([mu_g[q][k, j, i] for q in range(2)], axis=1)
+    del phi_g, mu_g
+    e_phi = [float(np.max(np.abs(ph[:, a] - z["phi"][:, a]))) / float(z["maxabs_phi"][a])
+             for a in range(4)]
+    e_mu = [float(np.max(np.abs(mu[:, q] - z["mu"][:, q]))) / float(z["maxabs_mu"][q])
+            for q in range(2)]
+    e_c = [abs(dg["sum_c"][q] - float(z["sum_c"][q])) / abs(float(z["sum_c"][q])) for q in range(2)]
+    log(f"c2 {steps} steps, {len(i)} cells: phi rel {max(e_phi):.2e}, mu rel {max(e_mu):.2e}, "
+        f"sum c rel {max(e_c):.2e}; kept {dg['fixed_items']}, pure mu {dg['mu_pure_items']}")
+    assert max(e_phi) <= 1e-12 and max(e_mu) <= 1e-12 and max(e_c) <= 1e-12
+    assert dg["step"] == steps and dg["nonfinite"] == 0
+    # the sample holds interface cells whose state the run changed
+    assert np.any((z["phi"] > 1e-3) & (z["phi"] < 1 - 1e-3))

@@ -73,6 +73,40 @@ def test_pack_matches_single_domain_bitwise(prec):
         d.close()
 
 
+def test_pack_member_refuses_reconfiguration():
+    """A member's descriptor and step budget belong to its pack's captured
+    step: set_params, init_fields and set_time on a member are refused with
+    STATE and leave it stepping as before; after removal they work again."""
+    import paper_1506_01684_amd as pfmod
+
+    pf = lib()
+    pf.set_variant(1)
+    w = _domains("fp64", 1, 5)[0]
+    log(f"case pack member refusal: {w['shape']}")
+    ref = _alone(pf, w)
+    pk = pf.Pack("fp64", max_domains=4)
+    d = pf.Domain(w["shape"], "fp64")
+    d.set_params(w["params"])
+    d.init_voronoi(w["seed"], w["nseeds"], w["hs"])
+    pk.add(d, w["steps"])
+    pk.step(2)
+    for call in (lambda: d.set_params(w["params"]),
+                 lambda: d.init_voronoi(w["seed"], w["nseeds"], w["hs"]),
+                 lambda: d.set_time(0)):
+        with pytest.raises(pfmod.PfError) as e:
+            call()
+        assert e.value.status == 2  # PF_ERR_STATE
+    pk.step(w["steps"])
+    assert pk.remaining(d) == 0 and d.step_index == w["steps"]
+    got = d.read()
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    pk.remove(d)
+    d.set_time(0)
+    assert d.step_index == 0
+    d.close()
+    pk.close()
+
+
 def test_pack_graph_replays_match_eager_oracle_on_small_domain():
     """A graph-replayed pack step equals the oracle (FP64, 1e-12)."""
     pf = lib()
