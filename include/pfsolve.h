@@ -296,6 +296,40 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path);
 pf_status pf_mesh_phase(pf_domain* d, int32_t phase, double iso, const pf_device_buffer* out,
                         int64_t* ntri);
 
+/* Diagnostics of fields the caller holds in device memory, computed
+ * without a domain and without allocating any memory.  For callers that
+ * cannot allocate (code that must not call hipMalloc: serving loops with a
+ * fixed footprint, harnesses that forbid allocation); not in the paper.
+ * The sums are those pf_read_fields reports (conserved concentrations of
+ * Eq. (3) under the frozen temperature, Sec. 2; sums of phi, the largest
+ * |sum_a phi_a - 1|, phi range, non-finite cells), from the same kernel
+ * arithmetic and reduction order, so for one state they are bitwise equal.
+ *   desc:   sizes, precision (element type of `fields`) and dx.
+ *   p:      only T0, G, v, zoff, TE, chi0, chi1, c0, c1 are read
+ *           (T(z,t) = T0 + G (z dx + zoff - v t)).
+ *   fields: device pointer to phi_0..3, mu_0, mu_1, each [z][y][x] with x
+ *           fastest, no padding, one field after the other (6 nx ny nz
+ *           elements); read only, still owned by the caller.
+ *   t:      the time the fields belong to (finite).
+ *   stream: hipStream_t to run on (NULL = null stream); the call waits for
+ *           its own result before it returns.
+ *   out:    filled like pf_read_fields' diag, with step = -1 and the item
+ *           counts and window shifts 0.
+ * Memory: partial sums go to a static device array of 480 x 10 + 10
+ * doubles (38.5 KiB) that each GPU the library runs on keeps until the
+ * process ends; its size does not depend on the domain, and every word a
+ * call reads it has written first, so nothing needs clearing.  All calls
+ * on one GPU share its array and it keeps the last call's values: calls
+ * that overlapped on one GPU would race, so the library serialises them
+ * with a host lock per device (the call returns only after its result is
+ * back).  Errors: INVALID_ARG for null or misaligned
+ * pointers, sizes <= 0, an unknown precision, fields beyond 2^62 bytes, a
+ * non-finite t or dx <= 0; DEVICE for HIP errors; NONFINITE (outputs
+ * filled) if any cell holds a NaN or Inf. */
+pf_status pf_diag_fields_noalloc(const pf_domain_desc* desc, const pf_params* p,
+                                 const void* fields, double t, void* stream,
+                                 pf_diag* out);
+
 /* Batched stepping (many independent domains of one precision).  Not in
  * the paper, which runs one large domain over many processes: batching
  * and serving of many independent solves are this library's use of one

@@ -15,7 +15,8 @@ import numpy as np
 
 from . import _capi as A
 
-__all__ = ["PfError", "Domain", "Pack", "load", "set_variant", "required_bytes"]
+__all__ = ["PfError", "Domain", "Pack", "load", "set_variant", "required_bytes",
+           "diag_fields_noalloc"]
 
 _lib = None
 _lock = threading.Lock()
@@ -103,6 +104,44 @@ def params_struct(p: dict) -> A.PfParams:
     fill = p.get("mu_fill", (0.0, 0.0))
     s.mu_fill[0], s.mu_fill[1] = float(fill[0]), float(fill[1])
     return s
+
+
+def _diag_dict(dg) -> dict:
+    return {
+        "t": dg.t, "step": dg.step, "sum_c": list(dg.sum_c), "sum_phi": list(dg.sum_phi),
+        "max_simplex_dev": dg.max_simplex_dev, "phi_min": dg.phi_min,
+        "phi_max": dg.phi_max, "nonfinite": dg.nonfinite,
+        "window_shifts": dg.window_shifts,
+        "light_items": dg.light_items, "work_items": dg.work_items,
+        "fixed_items": dg.fixed_items, "mu_pure_items": dg.mu_pure_items,
+        "copied_items": dg.copied_items,
+    }
+
+
+def diag_fields_noalloc(fields, params: dict, t: float, dx: float = 1.0, stream=None,
+                        raise_nonfinite: bool = True) -> dict:
+    """Diagnostics of a torch CUDA tensor ``fields`` of shape (6, nz, ny, nx)
+    (phi_0..3, mu_0, mu_1; float64 or float32, contiguous) at time t, by
+    pf_diag_fields_noalloc: no domain, no device allocation."""
+    import torch
+
+    if fields.dim() != 4 or fields.shape[0] != 6 or not fields.is_contiguous():
+        raise ValueError("fields must be a contiguous (6, nz, ny, nx) tensor")
+    if fields.dtype == torch.float64:
+        prec = A.PF_FP64
+    elif fields.dtype == torch.float32:
+        prec = A.PF_FP32
+    else:
+        raise ValueError("fields must be float64 or float32")
+    _, nz, ny, nx = (int(v) for v in fields.shape)
+    desc = A.PfDomainDesc(nx, ny, nz, prec, float(dx))
+    ps = params_struct(params)
+    dg = A.PfDiag()
+    st = load().pf_diag_fields_noalloc(C.byref(desc), C.byref(ps), C.c_void_p(fields.data_ptr()),
+                                       float(t), C.c_void_p(_stream_handle(stream)), C.byref(dg))
+    if st != A.PF_OK and (raise_nonfinite or st != A.PF_ERR_NONFINITE):
+        _check(st)
+    return _diag_dict(dg)
 
 
 class Domain:
@@ -255,15 +294,7 @@ class Domain:
         st = load().pf_read_fields(self.handle, None, None, C.byref(dg))
         if st != A.PF_OK and (raise_nonfinite or st != A.PF_ERR_NONFINITE):
             _check(st)
-        return {
-            "t": dg.t, "step": dg.step, "sum_c": list(dg.sum_c), "sum_phi": list(dg.sum_phi),
-            "max_simplex_dev": dg.max_simplex_dev, "phi_min": dg.phi_min,
-            "phi_max": dg.phi_max, "nonfinite": dg.nonfinite,
-            "window_shifts": dg.window_shifts,
-            "light_items": dg.light_items, "work_items": dg.work_items,
-            "fixed_items": dg.fixed_items, "mu_pure_items": dg.mu_pure_items,
-            "copied_items": dg.copied_items,
-        }
+        return _diag_dict(dg)
 
 
 class Pack:

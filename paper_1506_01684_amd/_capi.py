@@ -24,7 +24,7 @@ EXPORTS = [
     "pf_set_time", "pf_step", "pf_step_timed", "pf_sync", "pf_read_fields", "pf_get_step",
     "pf_destroy", "pf_pack_create", "pf_pack_add", "pf_pack_step", "pf_pack_remaining",
     "pf_pack_remove", "pf_pack_sync", "pf_pack_destroy", "pf_set_variant", "pf_last_error",
-    "pf_checkpoint_save", "pf_checkpoint_load", "pf_mesh_phase",
+    "pf_checkpoint_save", "pf_checkpoint_load", "pf_mesh_phase", "pf_diag_fields_noalloc",
 ]
 
 
@@ -100,6 +100,8 @@ def declare(lib: C.CDLL) -> C.CDLL:
         "pf_checkpoint_save": (C.c_int, [P, C.c_char_p]),
         "pf_checkpoint_load": (C.c_int, [P, C.c_char_p]),
         "pf_mesh_phase": (C.c_int, [P, I32, _D, C.POINTER(PfDeviceBuffer), C.POINTER(I64)]),
+        "pf_diag_fields_noalloc": (C.c_int, [C.POINTER(PfDomainDesc), C.POINTER(PfParams), P, _D,
+                                             P, C.POINTER(PfDiag)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -472,14 +472,14 @@ __global__ __launch_bounds__(256) void ghost_kernel(const DevDomain* dom) {
 // ---------------------------------------------------------- diagnostics
 
 // FP64 partial sums per work group (fixed grid, fixed reduction order, so
-// the result is reproducible run to run).
-template <typename R>
-__global__ __launch_bounds__(256) void diag_partial_kernel(const DevDomain* dom, double t,
-                                                           double* partials) {
-  const DevDomain& d = *dom;
-  const R* base = static_cast<const R*>(d.copy[d.parity]);
+// the result is reproducible run to run).  `d` supplies the sizes, the
+// element strides of `base` (plane, pitch, fstride), the temperature
+// (T0, G, dx, zoff, shifts, v, TE) and the concentration coefficients
+// (chi0, chi1, c0, c1): a DevDomain, or a DiagView of fields a caller holds.
+template <typename R, typename D>
+__device__ __forceinline__ void diag_partial_body(const D& d, const R* base, double t,
+                                                  double* partials) {
   const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
-  if (t < 0.0) t = (double)d.step * d.dt;
   double v[kDiagValues] = {0, 0, 0, 0, 0, 0, 0, __builtin_inf(), -__builtin_inf(), 0};
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -535,6 +535,20 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const DevDomain* dom,
     __syncthreads();
   }
   if (threadIdx.x < kDiagValues) partials[blockIdx.x * kDiagValues + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void diag_partial_kernel(const DevDomain* dom, double t,
+                                                           double* partials) {
+  const DevDomain& d = *dom;
+  if (t < 0.0) t = (double)d.step * d.dt;
+  diag_partial_body<R>(d, static_cast<const R*>(d.copy[d.parity]), t, partials);
+}
+
+// The same sums over fields passed by pointer (the view travels by value).
+template <typename R>
+__global__ __launch_bounds__(256) void diag_view_kernel(DiagView d, double t, double* partials) {
+  diag_partial_body<R>(d, static_cast<const R*>(d.base), t, partials);
 }
 
 __global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, int nblocks,
@@ -637,6 +651,16 @@ hipError_t launch_diag(const DevDomain* dom, int prec, int nx, int ny, int nz, d
     diag_partial_kernel<double><<<kDiagBlocks, 256, 0, s>>>(dom, t, partials);
   else
     diag_partial_kernel<float><<<kDiagBlocks, 256, 0, s>>>(dom, t, partials);
+  diag_final_kernel<<<1, 64, 0, s>>>(partials, kDiagBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_view(const DiagView& view, int prec, double t, double* partials,
+                            double* out, hipStream_t s) {
+  if (prec == 0)
+    diag_view_kernel<double><<<kDiagBlocks, 256, 0, s>>>(view, t, partials);
+  else
+    diag_view_kernel<float><<<kDiagBlocks, 256, 0, s>>>(view, t, partials);
   diag_final_kernel<<<1, 64, 0, s>>>(partials, kDiagBlocks, out);
   return hipGetLastError();
 }

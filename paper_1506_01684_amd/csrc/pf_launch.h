@@ -45,6 +45,20 @@ constexpr int kDiagBlocks = 480;
 constexpr int kDiagValues = 10;
 hipError_t launch_diag(const DevDomain* dom, int prec, int nx, int ny, int nz, double t,
                        double* partials, double* out, hipStream_t s);
+// The same diagnostics of six fields the caller holds: field f of cell
+// (x,y,z) at base[f fstride + z plane + y pitch + x] (elements of the
+// precision), with the temperature and concentration coefficients given
+// here instead of a domain's descriptor.
+struct DiagView {
+  const void* base;
+  int32_t nx, ny, nz;
+  int64_t pitch, plane, fstride;
+  double T0, G, dx, zoff, v, TE;
+  int64_t shifts;
+  double chi0[NP][NM], chi1[NP][NM], c0[NP][NM], c1[NP][NM];
+};
+hipError_t launch_diag_view(const DiagView& view, int prec, double t, double* partials,
+                            double* out, hipStream_t s);
 
 // Output path (pf_io.hip).  Checkpoints: the six fields of copy `src`
 // rounded to float into out[f][z][y][x] (cells = nx ny nz), and back into

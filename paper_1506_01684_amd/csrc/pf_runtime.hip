@@ -904,6 +904,99 @@ pf_status pf_mesh_phase(pf_domain* d, int32_t phase, double iso, const pf_device
 
 }  // extern "C"
 
+// ============================================= diagnostics without allocation
+
+// Scratch of pf_diag_fields_noalloc: the partial sums of the diagnostics'
+// fixed grid (kDiagBlocks x kDiagValues) and their final values, 38.5 KiB.
+// Each device the library runs on holds its own copy until the process
+// ends.  Host code never passes this name to a kernel or a copy: it stands
+// for the array only on the device side; the per-device address comes from
+// hipGetSymbolAddress below.
+constexpr size_t kNoAllocDoubles = (size_t)kDiagBlocks * kDiagValues + kDiagValues;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];    // one call at a time per device
+double* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_diag_fields_noalloc(const pf_domain_desc* desc, const pf_params* p,
+                                 const void* fields, double t, void* stream, pf_diag* out) {
+  if (!desc || !p || !fields || !out) return fail(PF_ERR_INVALID_ARG, "null argument");
+  if (desc->nx <= 0 || desc->ny <= 0 || desc->nz <= 0)
+    return fail(PF_ERR_INVALID_ARG, "sizes must be positive");
+  if (desc->prec != PF_FP64 && desc->prec != PF_FP32)
+    return fail(PF_ERR_INVALID_ARG, "unknown precision");
+  if (!(desc->dx > 0.0) || !std::isfinite(desc->dx))
+    return fail(PF_ERR_INVALID_ARG, "dx must be positive and finite");
+  if (!std::isfinite(t)) return fail(PF_ERR_INVALID_ARG, "t must be finite");
+  const size_t elem = desc->prec == PF_FP64 ? 8 : 4;
+  const long double bytes = (long double)desc->nx * desc->ny * desc->nz * NFIELD * elem;
+  if (bytes > (long double)(1ull << 62))
+    return fail(PF_ERR_INVALID_ARG, "fields larger than 2^62 bytes");
+  if (reinterpret_cast<uintptr_t>(fields) % elem != 0)
+    return fail(PF_ERR_INVALID_ARG, "fields not aligned to their element size");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PF_ERR_DEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(PF_ERR_INVALID_ARG, "device index beyond " + std::to_string(kMaxDevices - 1));
+  std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+  if (!g_scratch_ptr[dev]) {  // first call on this device, which is current
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PF_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  double* partials = g_scratch_ptr[dev];
+  double* final_v = partials + (size_t)kDiagBlocks * kDiagValues;
+  DiagView v{};
+  v.base = fields;
+  v.nx = desc->nx;
+  v.ny = desc->ny;
+  v.nz = desc->nz;
+  v.pitch = desc->nx;
+  v.plane = (int64_t)desc->nx * desc->ny;
+  v.fstride = v.plane * desc->nz;
+  v.T0 = p->T0;
+  v.G = p->G;
+  v.dx = desc->dx;
+  v.zoff = p->zoff;
+  v.v = p->v;
+  v.TE = p->TE;
+  v.shifts = 0;
+  std::memcpy(v.chi0, p->chi0, sizeof(v.chi0));
+  std::memcpy(v.chi1, p->chi1, sizeof(v.chi1));
+  std::memcpy(v.c0, p->c0, sizeof(v.c0));
+  std::memcpy(v.c1, p->c1, sizeof(v.c1));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double r[kDiagValues];
+  PF_HIP(launch_diag_view(v, desc->prec, t, partials, final_v, s));
+  PF_HIP(hipMemcpyAsync(r, final_v, sizeof(r), hipMemcpyDeviceToHost, s));
+  PF_HIP(hipStreamSynchronize(s));
+  std::memset(out, 0, sizeof(*out));
+  out->t = t;
+  out->step = -1;
+  out->sum_c[0] = r[0];
+  out->sum_c[1] = r[1];
+  for (int a = 0; a < NP; ++a) out->sum_phi[a] = r[2 + a];
+  out->max_simplex_dev = r[6];
+  out->phi_min = r[7];
+  out->phi_max = r[8];
+  out->nonfinite = (int64_t)r[9];
+  if (out->nonfinite > 0)
+    return fail(PF_ERR_NONFINITE, std::to_string(out->nonfinite) + " non-finite cells");
+  return PF_OK;
+}
+
+}  // extern "C"
+
 // ==================================================================== packs
 
 struct pf_pack {
