@@ -147,7 +147,8 @@ typedef struct {
                            * by the FP64 tiled sweep; 0 in FP32, with the
                            * direct variant, with the shortcuts off, and
                            * before the first step                         */
-  int32_t work_items;     /* work items per sweep of this domain           */
+  int32_t work_items;     /* work items per sweep of this domain (x-y
+                           * tiles times z chunks)                        */
   int32_t fixed_items;    /* work items of the last step whose phi the
                            * tiled sweep copied unchanged: every cell in and
                            * around them held one pure phase that its planes

@@ -56,9 +56,9 @@ struct Tiling {
   }
 };
 
-Tiling choose_tiling(int nx, int ny, int nz) {
+Tiling choose_tiling(int nx, int ny, int nz, int prec) {
   Tiling t;
-  t.tx = nx >= 48 ? 64 : 32;
+  t.tx = nx >= 48 && prec != PF_FP64 ? 64 : 32;
   t.ty = kTileThreads / t.tx;
   t.ntx = (nx + t.tx - 1) / t.tx;
   t.nty = (ny + t.ty - 1) / t.ty;
@@ -98,7 +98,7 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   const long double cells = (long double)pitch * d.ny * d.nz;
   if (cells * L.elem * 12 > (long double)(1ull << 62)) return false;
   {  // work items of the tiled sweeps must fit the 32-bit block index
-    const int64_t tx = d.nx >= 48 ? 64 : 32, ty = kTileThreads / tx;
+    const int64_t tx = d.nx >= 48 && d.prec != PF_FP64 ? 64 : 32, ty = kTileThreads / tx;
     const int64_t items = ((d.nx + tx - 1) / tx) * ((d.ny + ty - 1) / ty) * (int64_t)d.nz;
     if (items > (int64_t)1 << 28) return false;
   }
@@ -119,7 +119,7 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   L.off_coef = off;
   const size_t coef_sz = d.prec == PF_FP64 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
   off = align_up(off + coef_sz * (size_t)d.nz, kAlign);
-  const Tiling T = choose_tiling(d.nx, d.ny, d.nz);
+  const Tiling T = choose_tiling(d.nx, d.ny, d.nz, d.prec);
   L.off_jfree = off;  // one 32-bit word per work item of the tiled sweeps, then the counts
   off = align_up(off + sizeof(uint32_t) * ((size_t)count_base(T.blocks()) + kCountWords), kAlign);
   L.pflag_bytes = align_up((size_t)T.ntx * T.nty * T.nzc, kAlign);
@@ -377,7 +377,7 @@ pf_status pf_create_domain(const pf_domain_desc* desc, const pf_device_buffer* b
   if (!d) return fail(PF_ERR_OOM, "host allocation failed");
   d->desc = *desc;
   d->L = L;
-  d->T = choose_tiling(desc->nx, desc->ny, desc->nz);
+  d->T = choose_tiling(desc->nx, desc->ny, desc->nz, desc->prec);
   d->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&d->device) != hipSuccess) {
     delete d;
@@ -733,7 +733,7 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->mu_pure_items = (int32_t)counts[kCountPure];
     diag->copied_items = (int32_t)counts[kCountCopied];
     diag->reserved = 0;
-    diag->work_items = d->T.blocks();
+    diag->work_items = d->T.ntx * d->T.nty * d->T.nzc;  // without the launch's padding blocks
     if (diag->nonfinite > 0)
       return fail(PF_ERR_NONFINITE, std::to_string(diag->nonfinite) + " non-finite cells");
   }

@@ -1,6 +1,7 @@
 // pf_tiled.hip -- face-sharing z-marching variant of the two sweeps.
 //
-// A work group of 256 threads owns an x-y tile (64x4 or 32x8 columns) and
+// A work group of 256 threads owns an x-y tile (64x4 or 32x8 columns; FP64
+// always 32x8, whose halo ring is smaller) and
 // marches over a chunk of z planes.  The phi^n planes it needs are staged in
 // LDS with a one-cell halo ring (one plane for the isotropic phi-sweep,
 // a ring of three planes k-1, k, k+1 when tangential face gradients are
@@ -47,9 +48,14 @@ struct V4 {
   R v[4];
 };
 
+// LDS capacities per tile.  FP32 tiles are 64x4 (32x8 when nx < 48); FP64
+// tiles are always 32x8.
 constexpr int kMaxHalo = 400;  // (tx+2)(ty+2): 66*6 = 396, 34*10 = 340
 constexpr int kMaxFx = 264;    // ty (tx+1): 4*65 = 260, 8*33 = 264
-constexpr int kMaxFy = 320;    // (ty+1) tx: 5*64 = 320, 9*32 = 288
+template <typename R>
+constexpr int kHaloCap = sizeof(R) == 8 ? 340 : kMaxHalo;
+template <typename R>
+constexpr int kFyCap = sizeof(R) == 8 ? 288 : 320;  // (ty+1) tx: 5*64 = 320, 9*32 = 288
 
 // LDS ring of phi planes: NSLOT planes of (tx+2)(ty+2) cells.
 template <typename R, int NSLOT>
@@ -57,8 +63,8 @@ struct LdsPhi;
 
 template <int NSLOT>
 struct LdsPhi<double, NSLOT> {
-  double2 lo[NSLOT][kMaxHalo];  // phi_0, phi_1
-  double2 hi[NSLOT][kMaxHalo];  // phi_2, phi_3
+  double2 lo[NSLOT][kHaloCap<double>];  // phi_0, phi_1
+  double2 hi[NSLOT][kHaloCap<double>];  // phi_2, phi_3
   __device__ __forceinline__ V4<double> get(int s, int c) const {
     const double2 a = lo[s][c], b = hi[s][c];
     return {{a.x, a.y, b.x, b.y}};
@@ -87,7 +93,7 @@ template <typename R>
 struct LdsMu;
 template <>
 struct LdsMu<double> {
-  double2 m[kMaxHalo];
+  double2 m[kHaloCap<double>];
   __device__ __forceinline__ void get(int c, double out[NM]) const {
     const double2 v = m[c];
     out[0] = v.x;
@@ -485,7 +491,7 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
   constexpr int AHEAD = ANISO ? 2 : 1;  // plane loaded during iteration k: k + AHEAD
   __shared__ LdsPhi<R, NSLOT> s_phi;
   __shared__ R s_qx[NP][kMaxFx];  // Q of the x faces (their share in the cell above)
-  __shared__ R s_qy[NP][kMaxFy];
+  __shared__ R s_qy[NP][kFyCap<R>];
   __shared__ uint8_t s_jw[4];          // per-wave bytes of the item's classification word
   __shared__ int8_t s_pw[4];           // per-wave pure phase of the outputs (pure_phase_flag)
   __shared__ int8_t s_pe[2][4];        // the same for the first and last plane
@@ -814,7 +820,7 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
   __shared__ LdsMu<R> s_mu;         // mu^n of plane k
   __shared__ LdsPhi<R, 1> s_p1;     // phi^{n+1} of plane k
   __shared__ R s_fx[NM][kMaxFx];
-  __shared__ R s_fy[NM][kMaxFy];
+  __shared__ R s_fy[NM][kFyCap<R>];
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
 
@@ -1124,7 +1130,7 @@ struct BulkLds {
   LdsPhi<R, 1> phi;  // phi^n of plane k
   LdsMu<R> mu;       // mu^n of plane k
   R fx[NM][kMaxFx];
-  R fy[NM][kMaxFy];
+  R fy[NM][kFyCap<R>];
 };
 
 template <typename R>
@@ -1132,7 +1138,7 @@ __device__ __forceinline__ void mu_bulk_item(const ItemCtx<R>& X, BulkLds<R>& L,
   LdsPhi<R, 1>& s_phi = L.phi;
   LdsMu<R>& s_mu = L.mu;
   R (*s_fx)[kMaxFx] = L.fx;
-  R (*s_fy)[kMaxFy] = L.fy;
+  R (*s_fy)[kFyCap<R>] = L.fy;
   const int wave = t >> 6, lane = t & 63;
   {
     const TileGeo& G = X.G;

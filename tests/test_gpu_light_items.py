@@ -146,10 +146,11 @@ def test_bulk_skip_survives_a_checkpoint_save():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def _chunk_layout(shape):
-    """Tile and z chunk of the tiled sweeps (the rule the library applies)."""
+def _chunk_layout(shape, prec):
+    """Tile and z chunk of the tiled sweeps (the rule the library applies:
+    FP64 tiles are always 32x8, FP32 tiles 64x4 unless nx < 48)."""
     nz, ny, nx = shape
-    tx = 64 if nx >= 48 else 32
+    tx = 64 if nx >= 48 and prec != "fp64" else 32
     ty = 256 // tx
     ntx, nty = -(-nx // tx), -(-ny // ty)
     zc = min(32, max(8, nz * ntx * nty // 2048), nz)
@@ -223,7 +224,7 @@ def test_pure_item_count_matches_the_fields(prec, aniso, top_bc):
     phi1, _ = d.read()
     dg = d.diagnostics()
     d.close()
-    tx, ty, zc = _chunk_layout(shape)
+    tx, ty, zc = _chunk_layout(shape, prec)
     want = _expected_pure_items(_chunk_purity(phi0, tx, ty, zc), _chunk_purity(phi1, tx, ty, zc), top_bc)
     log(f"pure items {prec} top_bc={top_bc}: {dg['mu_pure_items']} (fields: {want}) of {dg['work_items']}")
     assert 0 < want < dg["work_items"]

@@ -9,8 +9,9 @@ import pytest
 KTHREADS, KXCD = 256, 8
 
 
-def tiling(nx, ny, nz):
-    tx = 64 if nx >= 48 else 32
+def tiling(nx, ny, nz, prec="fp32"):
+    # FP64 tiles are always 32x8; FP32 tiles 64x4 unless nx < 48
+    tx = 64 if nx >= 48 and prec != "fp64" else 32
     ty = KTHREADS // tx
     ntx, nty = -(-nx // tx), -(-ny // ty)
     cols = nz * ntx * nty
@@ -43,9 +44,10 @@ def decode(t, lb):
 
 @pytest.mark.parametrize("shape", [(512, 256, 256), (1024, 512, 512), (64, 32, 32), (20, 1, 1),
                                    (80, 70, 100), (300, 190, 33), (9, 17, 70), (128, 96, 96)])
-def test_blocks_cover_each_tile_once(shape):
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_blocks_cover_each_tile_once(shape, prec):
     nz, ny, nx = shape
-    t = tiling(nx, ny, nz)
+    t = tiling(nx, ny, nz, prec)
     assert t["blocks"] % 8 == 0
     seen = {}
     for lb in range(t["blocks"]):
