@@ -290,9 +290,11 @@ struct ItemCtx {
 // bit 1 when it saw only liquid.  Bits are set only with the shortcuts on
 // and mu not frozen; without the anti-trapping term every item qualifies.
 // The phi-sweep also counts the qualifying items of the step; the split
-// into two kernels is used only when they are at least kBulkMinPct percent
-// of all items: each kernel's last round of items runs on a partly idle
-// chip, which a small share of light items does not repay.
+// into two kernels is used only when those outside the chunks the phi bulk
+// shortcut kept (which are light too, and are mostly the pure items the
+// light kernel takes anyway) are at least kBulkMinPct percent of all items:
+// a light item costs that kernel about a whole round of pure items, and
+// a few of them are cheaper in the full kernel's own rounds.
 constexpr uint64_t kBulkMinPct = 60;
 constexpr uint32_t kBulkDone = 0x80000000u;  // item copied by the phi bulk shortcut
 constexpr uint32_t kMuPure = 0x40000000u;    // item taken by the pure-item body this step
@@ -305,10 +307,12 @@ __device__ __forceinline__ bool item_jfree(uint32_t f) {
 template <typename DD, typename CTX>
 __device__ __forceinline__ bool item_light(const DD& d, const CTX& X) {
   if (!item_jfree(*to_const(X.jf))) return false;
-  uint32_t n = 0;
+  int64_t n = 0;
 #pragma unroll
-  for (int sl = 0; sl < kCountSlots; ++sl) n += to_const(X.jc)[count_word(kCountLight, sl)];
-  return (uint64_t)n * 100 >= (uint64_t)d.nitems * kBulkMinPct;
+  for (int sl = 0; sl < kCountSlots; ++sl)
+    n += (int64_t)to_const(X.jc)[count_word(kCountLight, sl)] -
+         (int64_t)to_const(X.jc)[count_word(kCountFixed, sl)];
+  return n * 100 >= (int64_t)d.nitems * (int64_t)kBulkMinPct;
 }
 
 // jsel < 0: every item; 0: items that need the anti-trapping current;
@@ -1347,19 +1351,19 @@ __device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds
     // cell for planes z0 .. z1-1.  Only these loads go to global memory, so
     // a wait for plane k's values never waits for the loads issued after
     // them (the memory counter is in order).  The loads are unconditional:
-    // past the item's planes they read planes that zc keeps inside the
-    // buffer, and a thread without a halo cell reads its own column again;
-    // a load on only some paths made the compiler move its value between
-    // registers, waiting for it at once.
+    // past the item's planes they read its last needed plane again (a cache
+    // hit, not another plane from memory), and a thread without a halo cell
+    // reads its own column again; a load on only some paths made the
+    // compiler move its value between registers, waiting for it at once.
     R ro[kPureAhead][NM], rh[kPureAhead][NM];
     const bool halo = G.halo_c >= 0;
     const uint32_t hb = halo ? G.halo_b : G.own_b;
     const auto fetch = [&](int p, R o[NM], R hv[NM]) {
-      const int pc = g.zc(p);
+      const int pc = g.zc(p < z1 ? p : z1), ph = g.zc(p < z1 ? p : z1 - 1);
       o[0] = ldg<R>(src.at(4, pc), G.own_b);
       o[1] = ldg<R>(src.at(5, pc), G.own_b);
-      hv[0] = ldg<R>(src.at(4, pc), hb);
-      hv[1] = ldg<R>(src.at(5, pc), hb);
+      hv[0] = ldg<R>(src.at(4, ph), hb);
+      hv[1] = ldg<R>(src.at(5, ph), hb);
     };
 #pragma unroll
     for (int u = 0; u < kPureAhead; ++u) fetch(z0 + u, ro[u], rh[u]);
