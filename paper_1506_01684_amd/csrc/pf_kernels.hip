@@ -1,8 +1,9 @@
 // pf_kernels.hip -- HIP kernels of the phase-field time step for gfx950.
 //
-// One step (Algorithm 1 of the paper) is three launches on one stream:
-//   prologue: per-plane temperature coefficients of the step in FP64
-//             (Sec. 3.3), choice of source/destination copy, step counter;
+// One step (Algorithm 1 of the paper) is three stages on one stream:
+//   prologue: choice of source/destination copy, step counter, then the
+//             per-plane temperature coefficients of the step in FP64
+//             (Sec. 3.3);
 //   phi-sweep: phi_dst <- (phi_src, mu_src)             (Eqs. (1)-(2));
 //   mu-sweep:  mu_dst  <- (mu_src, phi_src, phi_dst)     (Eqs. (3)-(4)).
 // Boundaries are applied by index arithmetic (periodic x/y, mirror z), so
@@ -22,21 +23,18 @@ namespace pfk {
 
 // ------------------------------------------------------------- prologue
 
-// One work group per domain.  Evaluates the per-plane coefficients of step
-// n = d.step at t_n = n dt and t_{n+1} = (n+1) dt (products, never sums) in
-// FP64, rounds them to R, records the source copy, then advances the step
-// counter and the parity.  A domain whose step budget is spent is marked
-// inactive and left untouched.
-// z chunks whose fixed-point masks the prologue reduces in LDS.
-constexpr int kPrologueChunks = 1024;
-
+// One work group per domain.  Records the source copy of step n = d.step
+// (after a moving-window shift, if the front has passed the window plane),
+// zeroes the step's item counts, marks the first plane of every z chunk for
+// the fixed-point reduction of coef_kernel, then advances the step counter
+// and the parity.  A domain whose step budget is spent is marked inactive
+// and left untouched.
 template <typename R>
 __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, int ndom) {
   DevDomain& d = *doms[blockIdx.x];
   __shared__ int64_t s_step;
   __shared__ int s_src, s_act;
   __shared__ double s_red[256];
-  __shared__ int s_chunk[kPrologueChunks];  // fixed-point mask of each z chunk
   if (threadIdx.x == 0) {
     int act = d.steps_left != 0;
     s_act = act;
@@ -86,105 +84,10 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     shift = s_red[0] < 0.5 * (double)d.nx * (double)d.ny;
   }
   const int src = shift ? s_src ^ 1 : s_src;
-  const double zoff = d.zoff + (double)(d.shifts + shift) * d.dx;
   const int64_t n = s_step;
-  const double t0 = (double)n * d.dt, t1 = (double)(n + 1) * d.dt;
+  // each chunk's fixed-point mask starts full; coef_kernel ANDs every plane in
   PlaneCoef<R>* tab = static_cast<PlaneCoef<R>*>(d.coef);
-  const bool lds_chunks = d.nzc <= kPrologueChunks;  // else global atomics below
-  for (int i = threadIdx.x; i < kPrologueChunks; i += blockDim.x) s_chunk[i] = ~0;
-  __syncthreads();
-  for (int k = threadIdx.x; k < d.nz; k += blockDim.x) {
-    const double zc = (double)k * d.dx + zoff;
-    const double Tn = d.T0 + d.G * (zc - d.v * t0);
-    const double Tz = d.T0 + d.G * (zc + 0.5 * d.dx - d.v * t0);
-    const double Tn1 = d.T0 + d.G * (zc - d.v * t1);
-    PlaneCoef<R> c;
-    c.epsT = (R)(d.eps * Tn);
-    c.Toe = (R)(Tn / d.eps);
-    double chiN[NP][NM], cbN[NP][NM], chiZ[NP][NM], cbZ[NP][NM];
-    for (int a = 0; a < NP; ++a) {
-      c.wbar[a] = (R)(d.w0[a] + d.w1[a] * (Tn - d.TE));
-      for (int q = 0; q < NM; ++q) {
-        chiN[a][q] = d.chi0[a][q] + d.chi1[a][q] * (Tn - d.TE);
-        cbN[a][q] = d.c0[a][q] + d.c1[a][q] * (Tn - d.TE);
-        chiZ[a][q] = d.chi0[a][q] + d.chi1[a][q] * (Tz - d.TE);
-        cbZ[a][q] = d.c0[a][q] + d.c1[a][q] * (Tz - d.TE);
-        const double chiN1 = d.chi0[a][q] + d.chi1[a][q] * (Tn1 - d.TE);
-        const double cbN1 = d.c0[a][q] + d.c1[a][q] * (Tn1 - d.TE);
-        c.chi[a][q] = (R)chiN[a][q];
-        c.cbar[a][q] = (R)cbN[a][q];
-        c.Dchi[a][q] = (R)(d.D[a] * chiN[a][q]);
-        c.DchiZ[a][q] = (R)(d.D[a] * chiZ[a][q]);
-        c.chi1[a][q] = (R)chiN1;
-        c.dchi[a][q] = (R)(chiN1 - chiN[a][q]);
-        c.dcbar[a][q] = (R)(cbN1 - cbN[a][q]);
-      }
-    }
-    for (int a = 0; a < 3; ++a)
-      for (int q = 0; q < NM; ++q) {
-        c.dchiL[a][q] = (R)(chiN[LQ][q] - chiN[a][q]);
-        c.dcbL[a][q] = (R)(cbN[LQ][q] - cbN[a][q]);
-        c.dchiLZ[a][q] = (R)(chiZ[LQ][q] - chiZ[a][q]);
-        c.dcbLZ[a][q] = (R)(cbZ[LQ][q] - cbZ[a][q]);
-      }
-    // coefficients of the mu-sweep of pure items (mu_pure_item)
-    for (int a = 0; a < NP; ++a) {
-      R e[NP], h[NP];
-      for (int b = 0; b < NP; ++b) e[b] = b == a ? R(1) : R(0);
-      mu_cell_h<R>(e, h);
-      mu_face_m<R, false>(c, e, c.Mp[a]);
-      mu_face_m<R, true>(c, e, c.MpZ[a]);
-      for (int q = 0; q < NM; ++q) c.rchip[a][q] = rcp_(mu_cell_chi<R>(c, q, h));
-    }
-    // A pure cell (phi = e_a) whose face terms vanish (A = 0) is a fixed
-    // point when the cell stage maps it to e_a exactly.  Decided by running
-    // that cell stage (phi_cell in the path's precision) on e_a with A = 0:
-    // its driving force is zero for every finite mu (h = e_a, so
-    // psi_a - sum h psi = 0 and phi_b = 0 multiplies the rest), so mu = 0
-    // stands for any state.  As a guard against a different fusion of the
-    // same arithmetic where the sweep inlines it, the step must also keep
-    // a clear margin: rhs_a = 0, rhs_b = (T/eps) 16/pi^2 gamma_ab, so
-    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m) (m the mean), and
-    // the projection returns e_a when every y_b stays below y_a - 1; the
-    // margin is relative, plus an absolute 2^-20 for the rounding of y_a
-    // near 1 in FP32.
-    c.pure_fixed = 0;
-    for (int a = 0; a < NP; ++a) {
-      R e[NP], A[NP], m0[NM] = {R(0), R(0)};
-      for (int b = 0; b < NP; ++b) {
-        e[b] = b == a ? R(1) : R(0);
-        A[b] = R(0);
-      }
-      double out[NP];
-      phi_cell<R>(kparams<R>(d), c, e, m0, A, out);
-      bool fixed = true;
-      for (int b = 0; b < NP; ++b) fixed = fixed && (R)out[b] == e[b];
-      double rhs[NP], m = 0.0;
-      for (int b = 0; b < NP; ++b) {
-        rhs[b] = b == a ? 0.0 : (Tn / d.eps) * d.kp64.g16[a < b ? pair_index(a, b) : pair_index(b, a)];
-        m += rhs[b];
-      }
-      m *= 0.25;
-      const double thr = d.kp64.rate[a] * m;
-      for (int b = 0; b < NP; ++b) {
-        if (b == a) continue;
-        const double yb = -d.kp64.rate[b] * (rhs[b] - m);
-        fixed = fixed && yb + 1e-5 * (fabs(thr) + fabs(yb)) + 0x1p-20 < thr;
-      }
-      if (fixed) c.pure_fixed |= 1 << a;
-    }
-    c.chunk_fixed = ~0;
-    tab[k] = c;
-    if (lds_chunks) atomicAnd(&s_chunk[k / d.zc], c.pure_fixed);
-  }
-  __syncthreads();
-  // the fixed points of every plane of each z chunk, at its first plane
-  if (lds_chunks) {
-    for (int iz = threadIdx.x; iz < d.nzc; iz += blockDim.x) tab[iz * d.zc].chunk_fixed = s_chunk[iz];
-  } else {
-    for (int k = threadIdx.x; k < d.nz; k += blockDim.x)
-      atomicAnd(&tab[k / d.zc * d.zc].chunk_fixed, tab[k].pure_fixed);
-  }
+  for (int iz = threadIdx.x; iz < d.nzc; iz += blockDim.x) tab[iz * d.zc].chunk_fixed = ~0;
   __syncthreads();
   if (threadIdx.x == 0) {
     // the pure-phase flags of the copy this step writes are renewed by the
@@ -200,6 +103,143 @@ __global__ __launch_bounds__(256) void prologue_kernel(DevDomain* const* doms, i
     d.step = n + 1;
     d.parity = src ^ 1;
     if (d.steps_left > 0) d.steps_left -= 1;
+  }
+}
+
+// Per-plane coefficients of the running step n = d.cur_step at
+// t_n = n dt and t_{n+1} = (n+1) dt (products, never sums), evaluated in
+// FP64 and rounded to R (Sec. 3.3: everything that depends only on the
+// temperature once per z slice).  kCoefBlocks work groups per domain; four
+// threads per plane, thread a of a plane also evaluating what depends on
+// phase a (the pure-item coefficients and the fixed-point test), so that
+// the planes' longest chain is one phase's cell stage rather than four.
+// Each plane ANDs its fixed-point mask into its chunk's first record.
+template <typename R>
+__global__ __launch_bounds__(kCoefThreads) void coef_kernel(DevDomain* const* doms, int ndom) {
+  const DevDomain& d = *doms[blockIdx.x / kCoefBlocks];
+  if (!d.active) return;
+  const int a = threadIdx.x & 3;
+  const double zoff = d.zoff + (double)d.shifts * d.dx;
+  const int64_t n = d.cur_step;
+  const double t0 = (double)n * d.dt, t1 = (double)(n + 1) * d.dt;
+  PlaneCoef<R>* tab = static_cast<PlaneCoef<R>*>(d.coef);
+  for (int k0 = (blockIdx.x % kCoefBlocks) * (kCoefThreads / 4); k0 < d.nz;
+       k0 += kCoefBlocks * (kCoefThreads / 4)) {
+    const int k = k0 + (int)(threadIdx.x >> 2);
+    // every lane takes part in the shuffles below; lanes past the last
+    // plane evaluate plane nz-1 and write nothing
+    const int kc = k < d.nz ? k : d.nz - 1;
+    const double zc = (double)kc * d.dx + zoff;
+    const double Tn = d.T0 + d.G * (zc - d.v * t0);
+    const double Tz = d.T0 + d.G * (zc + 0.5 * d.dx - d.v * t0);
+    const double Tn1 = d.T0 + d.G * (zc - d.v * t1);
+    PlaneCoef<R> c;
+    c.epsT = (R)(d.eps * Tn);
+    c.Toe = (R)(Tn / d.eps);
+    double chiN[NP][NM], cbN[NP][NM], chiZ[NP][NM], cbZ[NP][NM];
+    for (int b = 0; b < NP; ++b) {
+      c.wbar[b] = (R)(d.w0[b] + d.w1[b] * (Tn - d.TE));
+      for (int q = 0; q < NM; ++q) {
+        chiN[b][q] = d.chi0[b][q] + d.chi1[b][q] * (Tn - d.TE);
+        cbN[b][q] = d.c0[b][q] + d.c1[b][q] * (Tn - d.TE);
+        chiZ[b][q] = d.chi0[b][q] + d.chi1[b][q] * (Tz - d.TE);
+        cbZ[b][q] = d.c0[b][q] + d.c1[b][q] * (Tz - d.TE);
+        const double chiN1 = d.chi0[b][q] + d.chi1[b][q] * (Tn1 - d.TE);
+        const double cbN1 = d.c0[b][q] + d.c1[b][q] * (Tn1 - d.TE);
+        c.chi[b][q] = (R)chiN[b][q];
+        c.cbar[b][q] = (R)cbN[b][q];
+        c.Dchi[b][q] = (R)(d.D[b] * chiN[b][q]);
+        c.DchiZ[b][q] = (R)(d.D[b] * chiZ[b][q]);
+        c.chi1[b][q] = (R)chiN1;
+        c.dchi[b][q] = (R)(chiN1 - chiN[b][q]);
+        c.dcbar[b][q] = (R)(cbN1 - cbN[b][q]);
+      }
+    }
+    for (int b = 0; b < 3; ++b)
+      for (int q = 0; q < NM; ++q) {
+        c.dchiL[b][q] = (R)(chiN[LQ][q] - chiN[b][q]);
+        c.dcbL[b][q] = (R)(cbN[LQ][q] - cbN[b][q]);
+        c.dchiLZ[b][q] = (R)(chiZ[LQ][q] - chiZ[b][q]);
+        c.dcbLZ[b][q] = (R)(cbZ[LQ][q] - cbZ[b][q]);
+      }
+    // coefficients of the mu-sweep of pure-a items (mu_pure_item)
+    R e[NP], h[NP], Mp[NM], MpZ[NM], rchip[NM];
+    for (int b = 0; b < NP; ++b) e[b] = b == a ? R(1) : R(0);
+    mu_cell_h<R>(e, h);
+    mu_face_m<R, false>(c, e, Mp);
+    mu_face_m<R, true>(c, e, MpZ);
+    for (int q = 0; q < NM; ++q) rchip[q] = rcp_(mu_cell_chi<R>(c, q, h));
+    // A pure cell (phi = e_a) whose face terms vanish (A = 0) is a fixed
+    // point when the cell stage maps it to e_a exactly.  Decided by running
+    // that cell stage (phi_cell in the path's precision) on e_a with A = 0:
+    // its driving force is zero for every finite mu (h = e_a, so
+    // psi_a - sum h psi = 0 and phi_b = 0 multiplies the rest), so mu = 0
+    // stands for any state.  As a guard against a different fusion of the
+    // same arithmetic where the sweep inlines it, the step must also keep
+    // a clear margin: rhs_a = 0, rhs_b = (T/eps) 16/pi^2 gamma_ab, so
+    // y_a = 1 + rate_a m and y_b = -rate_b (rhs_b - m) (m the mean), and
+    // the projection returns e_a when every y_b stays below y_a - 1; the
+    // margin is relative, plus an absolute 2^-20 for the rounding of y_a
+    // near 1 in FP32.
+    bool fixed;
+    {
+      R A[NP], m0[NM] = {R(0), R(0)};
+      for (int b = 0; b < NP; ++b) A[b] = R(0);
+      double out[NP];
+      phi_cell<R>(kparams<R>(d), c, e, m0, A, out);
+      fixed = true;
+      for (int b = 0; b < NP; ++b) fixed = fixed && (R)out[b] == e[b];
+      double rhs[NP], m = 0.0;
+      for (int b = 0; b < NP; ++b) {
+        rhs[b] = b == a ? 0.0 : (Tn / d.eps) * d.kp64.g16[a < b ? pair_index(a, b) : pair_index(b, a)];
+        m += rhs[b];
+      }
+      m *= 0.25;
+      const double thr = d.kp64.rate[a] * m;
+      for (int b = 0; b < NP; ++b) {
+        if (b == a) continue;
+        const double yb = -d.kp64.rate[b] * (rhs[b] - m);
+        fixed = fixed && yb + 1e-5 * (fabs(thr) + fabs(yb)) + 0x1p-20 < thr;
+      }
+    }
+    // the four phases' bits of the plane (lanes 4j .. 4j+3 of the wave)
+    int bits = fixed ? 1 << a : 0;
+    bits |= __shfl_xor(bits, 1);
+    bits |= __shfl_xor(bits, 2);
+    if (k >= d.nz) continue;
+    PlaneCoef<R>& o = tab[k];
+    for (int q = 0; q < NM; ++q) {
+      o.Mp[a][q] = Mp[q];
+      o.MpZ[a][q] = MpZ[q];
+      o.rchip[a][q] = rchip[q];
+    }
+    if (a != 0) continue;
+    o.epsT = c.epsT;
+    o.Toe = c.Toe;
+    for (int b = 0; b < NP; ++b) {
+      o.wbar[b] = c.wbar[b];
+      for (int q = 0; q < NM; ++q) {
+        o.chi[b][q] = c.chi[b][q];
+        o.cbar[b][q] = c.cbar[b][q];
+        o.Dchi[b][q] = c.Dchi[b][q];
+        o.DchiZ[b][q] = c.DchiZ[b][q];
+        o.chi1[b][q] = c.chi1[b][q];
+        o.dchi[b][q] = c.dchi[b][q];
+        o.dcbar[b][q] = c.dcbar[b][q];
+      }
+    }
+    for (int b = 0; b < 3; ++b)
+      for (int q = 0; q < NM; ++q) {
+        o.dchiL[b][q] = c.dchiL[b][q];
+        o.dcbL[b][q] = c.dcbL[b][q];
+        o.dchiLZ[b][q] = c.dchiLZ[b][q];
+        o.dcbLZ[b][q] = c.dcbLZ[b][q];
+      }
+    o.pure_fixed = bits;
+    // the fixed points of every plane of each z chunk, at its first plane
+    // (set to all ones by the prologue; other planes keep all ones)
+    if (k % d.zc != 0) o.chunk_fixed = ~0;
+    atomicAnd(&tab[k / d.zc * d.zc].chunk_fixed, bits);
   }
 }
 
@@ -566,10 +606,13 @@ __global__ __launch_bounds__(64) void diag_final_kernel(const double* partials, 
 // --------------------------------------------------------------- launches
 
 hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s) {
-  if (prec == 0)
+  if (prec == 0) {
     prologue_kernel<double><<<L.ndom, 256, 0, s>>>(L.doms, L.ndom);
-  else
+    coef_kernel<double><<<L.ndom * kCoefBlocks, kCoefThreads, 0, s>>>(L.doms, L.ndom);
+  } else {
     prologue_kernel<float><<<L.ndom, 256, 0, s>>>(L.doms, L.ndom);
+    coef_kernel<float><<<L.ndom * kCoefBlocks, kCoefThreads, 0, s>>>(L.doms, L.ndom);
+  }
   return hipGetLastError();
 }
 

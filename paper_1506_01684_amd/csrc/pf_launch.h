@@ -25,6 +25,11 @@ constexpr int kTileWaves = kTileThreads / 64;
 // Most z planes per work item of the tiled sweeps.
 constexpr int kMaxZc = 32;
 
+// The step's prologue: prologue_kernel (one work group per domain: copy
+// choice, window decision, counters, step counter), then coef_kernel
+// (kCoefBlocks work groups of kCoefThreads per domain: the per-plane
+// coefficient table).
+constexpr int kCoefBlocks = 16, kCoefThreads = 128;
 hipError_t launch_prologue(const LaunchSet& L, int prec, hipStream_t s);
 hipError_t launch_window(const LaunchSet& L, int prec, hipStream_t s);
 hipError_t launch_ghost(const DevDomain* dom, int prec, int nx, int ny, hipStream_t s);
