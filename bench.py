@@ -529,10 +529,25 @@ def run_cpu_baseline(workload: str, budget_s: float = 20.0) -> dict:
                     break
     except OSError:
         pass
+    # the small workload in full (100 steps), on one thread and on all
+    w1 = pfinputs.workload("c1")
+    s1 = w1["shape"]
+    p1 = pfinputs.with_dt(w1["params"], oracle.default_dt(w1["params"], s1))
+    c1_cells = s1[0] * s1[1] * s1[2]
+    c1 = {}
+    for nt in (1, threads):
+        ph1, mu1 = oracle.init_voronoi(s1, w1["seed"], w1["nseeds"], w1["solid_height"])
+        t1 = time.perf_counter()
+        oracle.run(p1, ph1, mu1, 100, nthreads=nt)
+        c1[nt] = c1_cells * 100 / (time.perf_counter() - t1) / 1e6
     return {
         "value": cells * n / el / 1e6, "unit": "MLUP/s", "cores": threads, "kind": "oracle",
         "sample": f"{n} full step(s) of the {shape[2]}x{shape[1]}x{shape[0]} FP64 domain "
                   f"from its Voronoi state, z planes split over {threads} threads, {el:.1f} s",
+        "small_workload_full": {
+            "workload": f"{s1[2]}x{s1[1]}x{s1[0]} FP64, 100 steps from its Voronoi state",
+            "one_thread_mlups": round(c1[1], 3), "all_threads_mlups": round(c1[threads], 3),
+            "threads": threads},
         "host": {"cpu": cpu, "nproc": os.cpu_count()},
     }
 
