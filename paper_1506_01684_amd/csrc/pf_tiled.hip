@@ -1355,8 +1355,11 @@ __device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds
     // hit, not another plane from memory), and a thread without a halo cell
     // reads its own column again; a load on only some paths made the
     // compiler move its value between registers, waiting for it at once.
+    // The four corners of the halo ring are not read (the stencil here has
+    // no tangential part), so their threads take no halo cell either.
     R ro[kPureAhead][NM], rh[kPureAhead][NM];
-    const bool halo = G.halo_c >= 0;
+    const bool corner = t == 0 || t == G.tx + 1 || t == G.tx + 2 || t == 2 * G.tx + 3;
+    const bool halo = G.halo_c >= 0 && !corner;
     const uint32_t hb = halo ? G.halo_b : G.own_b;
     const auto fetch = [&](int p, R o[NM], R hv[NM]) {
       const int pc = g.zc(p < z1 ? p : z1), ph = g.zc(p < z1 ? p : z1 - 1);
