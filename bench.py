@@ -44,6 +44,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 VALUES_PER_CELL = {"phi": 10, "mu": 12}
+# VALU issue peaks from the published vector rates and the unit counts
+# (256 CUs at 2.4 GHz, 64 lanes per wave instruction, two flops per lane of
+# an FMA): FP64 78.6 TFLOP/s is 78.6e12 / 128 = 6.144e11 wave instructions/s,
+# one per clock per CU; FP32 157.3 TFLOP/s is twice that.  The counts are of
+# every VALU instruction (address arithmetic, moves and selects included),
+# so the fraction is an issue-rate utilisation.
+VALU_PEAK_WIPS = {"double": 256 * 2.4e9, "float": 2 * 256 * 2.4e9}
 
 
 def _log(msg):
@@ -157,6 +164,15 @@ def sweep_rooflines(run: dict, real: str, aniso: bool, workload: str, variant: i
                   "frac": round(run[f"{k}_gbs"] / HBM_PEAK_GBS, 4),
                   "effective_gbs": round(run[f"{k}_effective_gbs"], 1),
                   "traffic": None if tr is None else round(tr)}
+        # the ALU side of the same sweep: recorded VALU wave instructions per
+        # launch (shortcuts on only; none recorded for the plain runs) over
+        # the live sweep time, against the issue peak
+        va = recorded_valu(kn, workload) if variant == 1 and not plain else None
+        if va is not None:
+            wips, peak = va / (run[f"{k}_ms"] * 1e-3), VALU_PEAK_WIPS[real]
+            out[k]["alu"] = {"bound": "alu", "valu_wave_insts_per_launch": round(va),
+                             "achieved": round(wips / 1e9, 2), "peak": round(peak / 1e9, 1),
+                             "unit": "G wave-instructions/s", "frac": round(wips / peak, 4)}
     return out
 
 
@@ -346,6 +362,29 @@ def recorded_traffic(kernel: str, workload: str):
         if not k:
             return None
         total += (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
+    return total
+
+
+def recorded_valu(kernel: str, workload: str):
+    """VALU wave instructions per launch of `kernel` (several joined by '+'
+    are summed) on `workload`, from the committed rocprofv3 SQ summary
+    (profiles/sq_counters.md); None when no summary matches the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "sq_counters.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    total = 0.0
+    for name in kernel.split("+"):
+        k = rec.get("kernels", {}).get(workload, {}).get(name)
+        if not k:
+            return None
+        total += k["valu_insts"]
     return total
 
 

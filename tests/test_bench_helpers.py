@@ -60,3 +60,25 @@ def test_owed_bytes_follow_the_item_classes():
     for sc, var in ((0, 1), (1, 0)):
         o = bench.owed_bytes(d0, d1, cells, es, sc, var)
         assert o["phi"] == 10 * cells * es and o["mu"] == 12 * cells * es
+
+
+def test_valu_counts_are_used_only_for_matching_sources(tmp_path, monkeypatch):
+    digest = bench.kernel_source_digest()
+    root = _fake_root(tmp_path, digest)
+    rec = {"kernel_source_sha256": digest,
+           "kernels": {"c3": {"mu_pure_f32": {"valu_insts": 10.0, "grbm_gui_active": 1.0},
+                              "mu_tiled_f32": {"valu_insts": 32.0, "grbm_gui_active": 1.0}}}}
+    (root / "profiles" / "sq_counters.md").write_text(
+        "# SQ\n\n```json\n" + json.dumps(rec) + "\n```\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.recorded_valu("mu_pure_f32+mu_tiled_f32", "c3") == 42.0
+    assert bench.recorded_valu("mu_tiled_f64", "c3") is None
+    src = root / "paper_1506_01684_amd" / "csrc" / "pf_device.h"
+    src.write_text(src.read_text() + "\n// changed\n")
+    assert bench.recorded_valu("mu_pure_f32+mu_tiled_f32", "c3") is None
+
+
+def test_valu_peaks_follow_the_published_rates():
+    # 64 lanes x 2 flops per FMA wave instruction
+    assert abs(bench.VALU_PEAK_WIPS["double"] * 128 / 1e12 - 78.6) < 0.1
+    assert abs(bench.VALU_PEAK_WIPS["float"] * 128 / 1e12 - 157.3) < 0.1
