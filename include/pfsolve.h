@@ -173,7 +173,9 @@ typedef struct {
  * paper: the memory budget of the serving loop (admission against HBM)
  * needs it.  The two copies are Algorithm 1's source and destination
  * fields; the layout is structure of arrays, x fastest, rows padded to
- * 128 bytes.  INVALID_ARG for sizes <= 0 or a total that overflows. */
+ * 128 bytes.  INVALID_ARG for sizes <= 0, a field plane of 4 GiB or more
+ * (padded row bytes times ny: the sweeps address a plane with 32-bit byte
+ * offsets) or a total that overflows. */
 pf_status pf_required_bytes(const pf_domain_desc* desc, size_t* out);
 
 /* Create a domain on the current HIP device: the regular grid of
@@ -182,7 +184,7 @@ pf_status pf_required_bytes(const pf_domain_desc* desc, size_t* out);
  * lifetime management.  borrowed: NULL = allocate, else a caller-owned
  * device buffer of at least pf_required_bytes() that must outlive the
  * domain.  stream: a hipStream_t (NULL = null stream).  Errors:
- * INVALID_ARG for sizes <= 0 or overflowing, OOM, DEVICE. */
+ * INVALID_ARG for sizes that pf_required_bytes rejects, OOM, DEVICE. */
 pf_status pf_create_domain(const pf_domain_desc* desc,
                            const pf_device_buffer* borrowed, void* stream,
                            pf_domain** out);

@@ -94,6 +94,9 @@ bool make_layout(const pf_domain_desc& d, Layout& L) {
   const int64_t row_elems = 128 / (int64_t)L.elem;
   const int64_t pitch = (d.nx + row_elems - 1) / row_elems * row_elems;
   if (pitch > INT32_MAX) return false;
+  // the tiled sweeps address a cell within its field plane by a 32-bit byte
+  // offset: a plane (pitch x ny elements) must stay below 4 GiB
+  if ((uint64_t)pitch * (uint64_t)d.ny * L.elem > (uint64_t)UINT32_MAX) return false;
   L.pitch = (int32_t)pitch;
   const long double cells = (long double)pitch * d.ny * d.nz;
   if (cells * L.elem * 12 > (long double)(1ull << 62)) return false;

@@ -45,6 +45,20 @@ def test_required_bytes_layout_and_validation():
         pf.required_bytes((4, 4, 4), "fp64", dx=0.0)
 
 
+@pytest.mark.parametrize("prec,nx", [("fp64", 16), ("fp32", 32), ("fp64", 20)])
+def test_required_bytes_caps_a_field_plane_below_4_gib(prec, nx):
+    # rows are padded to a multiple of 128 bytes; with 128-byte rows the
+    # largest plane is 2^32 - 128 bytes (2^25 - 1 rows) and one more row
+    # reaches 2^32; nx = 20 FP64 pads to 32 elements (256-byte rows)
+    row = -(-nx * (8 if prec == "fp64" else 4) // 128) * 128
+    ny_max = (2 ** 32 - 1) // row
+    big = pf.required_bytes((1, ny_max, nx), prec)
+    assert big >= 2 * 6 * ny_max * row
+    with pytest.raises(pf.PfError) as e:
+        pf.required_bytes((1, ny_max + 1, nx), prec)
+    assert "INVALID_ARG" in str(e.value)
+
+
 def test_variant_switch_validates():
     with pytest.raises(pf.PfError):
         pf.set_variant(7)
