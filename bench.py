@@ -262,8 +262,26 @@ def run_output(steps: int = 20, reps: int = 5) -> dict:
         t2 = time.perf_counter()
         out["checkpoint"] = {"bytes": os.path.getsize(path), "save_s": round(t1 - t0, 3),
                              "load_s": round(t2 - t1, 3)}
+    # the host side of the boundary: all six fields to host memory as FP64
+    # (pf_read_fields) and back (pf_init_fields from host arrays)
+    t0 = time.perf_counter()
+    phi, mu = d.read()
+    t1 = time.perf_counter()
+    d.init_host(phi, mu)
+    d.sync()
+    t2 = time.perf_counter()
+    out["host_copy"] = {"field_bytes": 6 * 8 * nx * ny * nz, "read_s": round(t1 - t0, 3),
+                        "init_s": round(t2 - t1, 3)}
     d.close()
     return out
+
+
+def pcie_inclusive_mlups(cells: int, steps: int, ms_per_step: float, host_copy: dict) -> float:
+    """Rate of a whole job that starts from host arrays and ends in host
+    arrays: one pf_init_fields from the host, `steps` steps, one
+    pf_read_fields (never the bench value, which starts from HBM)."""
+    t = host_copy["init_s"] + host_copy["read_s"] + steps * ms_per_step * 1e-3
+    return cells * steps / t / 1e6
 
 
 def run_stream(nbytes: int = 2 << 30, reps: int = 10) -> dict:
@@ -713,6 +731,9 @@ def main():
     if not args.no_output and args.workload == "c2":
         _log("[bench] output path: meshes and checkpoint")
         line["output"] = run_output()
+        hc = line["output"]["host_copy"]
+        hc["pcie_inclusive_mlups_1000_steps"] = round(
+            pcie_inclusive_mlups(main_run["cells"], 1000, main_run["ms_per_step"], hc), 1)
     if not args.no_fp32 and args.workload == "c2":
         r32 = run_gpu("c3", args.fp32_steps, 5, args.variant, args.shortcuts)
         line["fp32"] = {

@@ -82,3 +82,12 @@ def test_valu_peaks_follow_the_published_rates():
     # 64 lanes x 2 flops per FMA wave instruction
     assert abs(bench.VALU_PEAK_WIPS["double"] * 128 / 1e12 - 78.6) < 0.1
     assert abs(bench.VALU_PEAK_WIPS["float"] * 128 / 1e12 - 157.3) < 0.1
+
+
+def test_pcie_inclusive_rate_counts_both_copies_and_the_steps():
+    # 1e6 cells, 1000 steps of 1 ms, 0.5 s in and 0.5 s out: 1e9 LUP in 2 s
+    hc = {"init_s": 0.5, "read_s": 0.5}
+    assert abs(bench.pcie_inclusive_mlups(1_000_000, 1000, 1.0, hc) - 500.0) < 1e-9
+    # without host copies it is the step rate itself
+    assert abs(bench.pcie_inclusive_mlups(1_000_000, 1000, 1.0, {"init_s": 0, "read_s": 0})
+               - 1000.0) < 1e-9
