@@ -210,7 +210,10 @@ pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
  * solid phase s mod 3; each column takes the nearest seed by periodic
  * minimum-image distance from its centre (i+1/2, j+1/2), lowest index on
  * ties; z < solid_height is solid, the rest liquid; mu = mu_init.
- * HOST: copy (and for FP32 round) the caller's arrays.  Synchronises. */
+ * HOST: copy (and for FP32 round) the caller's arrays, phi[4][nz][ny][nx]
+ * and mu[2][nz][ny][nx] (host memory, read only, still owned by the
+ * caller); each field passes through the domain's second field copy on the
+ * device, so no memory is allocated.  Synchronises. */
 pf_status pf_init_fields(pf_domain* d, const pf_init* init);
 
 /* Resume from a checkpoint (Sec. 3.2 checkpointing): the next step is
@@ -239,9 +242,14 @@ pf_status pf_step_timed(pf_domain* d, int64_t n, double* phi_ms,
 pf_status pf_sync(pf_domain* d);
 
 /* Copy the current state to host (FP32 widened to FP64) and/or compute the
- * diagnostics of the current state; any pointer may be NULL.  Synchronises.
- * Returns NONFINITE (after filling the outputs) if the diagnostics count any
- * non-finite cell. */
+ * diagnostics of the current state; any pointer may be NULL.  phi and mu
+ * are caller-owned host arrays of 4 and 2 times nx ny nz doubles, laid out
+ * as for pf_init_fields.  Each field is packed on the device into the
+ * copy that does not hold the state (no memory is allocated); the state is
+ * unchanged, and the next step's bulk shortcut copies the chunks it would
+ * otherwise have found in both copies.  Synchronises.  Returns NONFINITE
+ * (after filling the outputs) if the diagnostics count any non-finite
+ * cell. */
 pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag);
 
 /* Number of completed steps of the current state: the time level n of

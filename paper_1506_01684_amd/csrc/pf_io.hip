@@ -60,6 +60,34 @@ __global__ __launch_bounds__(256) void ckpt_unpack_kernel(const DevDomain* dom, 
   }
 }
 
+// One field of a copy as dense FP64 [z][y][x] (host readback), and back
+// (host initialisation, rounded to the domain's precision).
+template <typename R>
+__global__ __launch_bounds__(256) void field_pack_kernel(const DevDomain* dom, int src, int f,
+                                                         double* out) {
+  const DevDomain& d = *dom;
+  const R* base = static_cast<const R*>(d.copy[src]) + f * d.fstride;
+  const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = c % d.nx, r = c / d.nx;
+    out[c] = (double)base[(r / d.ny) * d.plane + (r % d.ny) * d.pitch + x];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void field_unpack_kernel(const DevDomain* dom, int dst, int f,
+                                                           const double* in) {
+  const DevDomain& d = *dom;
+  R* base = static_cast<R*>(d.copy[dst]) + f * d.fstride;
+  const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = c % d.nx, r = c / d.nx;
+    base[(r / d.ny) * d.plane + (r % d.ny) * d.pitch + x] = (R)in[c];
+  }
+}
+
 namespace {
 int grid_for(int64_t items) {
   const int64_t b = (items + 255) / 256;
@@ -82,6 +110,24 @@ hipError_t launch_ckpt_unpack(const DevDomain* dom, int prec, int64_t cells, int
     ckpt_unpack_kernel<double><<<grid_for(cells), 256, 0, s>>>(dom, dst, in);
   else
     ckpt_unpack_kernel<float><<<grid_for(cells), 256, 0, s>>>(dom, dst, in);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_pack(const DevDomain* dom, int prec, int64_t cells, int src, int f,
+                             double* out, hipStream_t s) {
+  if (prec == 0)
+    field_pack_kernel<double><<<grid_for(cells), 256, 0, s>>>(dom, src, f, out);
+  else
+    field_pack_kernel<float><<<grid_for(cells), 256, 0, s>>>(dom, src, f, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_unpack(const DevDomain* dom, int prec, int64_t cells, int dst, int f,
+                               const double* in, hipStream_t s) {
+  if (prec == 0)
+    field_unpack_kernel<double><<<grid_for(cells), 256, 0, s>>>(dom, dst, f, in);
+  else
+    field_unpack_kernel<float><<<grid_for(cells), 256, 0, s>>>(dom, dst, f, in);
   return hipGetLastError();
 }
 

@@ -74,6 +74,15 @@ hipError_t launch_ckpt_pack(const DevDomain* dom, int prec, int64_t cells, int s
                             hipStream_t s);
 hipError_t launch_ckpt_unpack(const DevDomain* dom, int prec, int64_t cells, int dst,
                               const float* in, hipStream_t s);
+// Clear the both-copies mark of n chunk flags of the current copy, after
+// the other copy has served as host staging.
+hipError_t launch_drop_same(uint8_t* flags, int64_t n, hipStream_t s);
+// Host boundary: field f of copy `src` as dense FP64 out[z][y][x], and
+// dense FP64 in[z][y][x] rounded into field f of copy `dst`.
+hipError_t launch_field_pack(const DevDomain* dom, int prec, int64_t cells, int src, int f,
+                             double* out, hipStream_t s);
+hipError_t launch_field_unpack(const DevDomain* dom, int prec, int64_t cells, int dst, int f,
+                               const double* in, hipStream_t s);
 hipError_t launch_mesh(const DevDomain* dom, int prec, int64_t rows, int phase, double iso,
                        float* out, int64_t cap, unsigned long long* count, hipStream_t s);
 

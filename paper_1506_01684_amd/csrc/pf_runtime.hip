@@ -560,24 +560,19 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
     PF_HIP(hipStreamSynchronize(d->stream));
   } else if (in->kind == PF_INIT_HOST) {
     if (!in->phi || !in->mu) return fail(PF_ERR_INVALID_ARG, "HOST init needs phi and mu");
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    std::vector<char> buf(L.copy_bytes, 0);
+    // each field goes to copy 1 as dense FP64 (a copy holds at least
+    // 8 bytes per cell and field: six fields of at least 4 bytes), and a
+    // kernel rounds it into copy 0; padding and the ghost planes of copy 0
+    // start at zero
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    double* stage = reinterpret_cast<double*>(d->fields(1));
+    PF_HIP(hipMemsetAsync(d->fields(0), 0, L.copy_bytes, d->stream));
     for (int f = 0; f < NFIELD; ++f) {
       const double* srcf = f < NP ? in->phi + (size_t)f * n : in->mu + (size_t)(f - NP) * n;
-      for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y) {
-          const double* row = srcf + ((size_t)z * g.ny + y) * g.nx;
-          const size_t o = (size_t)f * L.fstride + (size_t)z * L.plane + (size_t)y * L.pitch;
-          if (g.prec == PF_FP64) {
-            std::memcpy(buf.data() + o * 8, row, sizeof(double) * g.nx);
-          } else {
-            float* dstp = reinterpret_cast<float*>(buf.data()) + o;
-            for (int x = 0; x < g.nx; ++x) dstp[x] = (float)row[x];
-          }
-        }
+      PF_HIP(hipMemcpyAsync(stage, srcf, sizeof(double) * (size_t)n, hipMemcpyHostToDevice,
+                            d->stream));
+      PF_HIP(launch_field_unpack(d->dev, g.prec, n, 0, f, stage, d->stream));
     }
-    PF_HIP(hipMemcpyAsync(d->fields(0), buf.data(), L.copy_bytes, hipMemcpyHostToDevice,
-                          d->stream));
     PF_HIP(hipStreamSynchronize(d->stream));
   } else {
     return fail(PF_ERR_INVALID_ARG, "unknown init kind");
@@ -689,27 +684,28 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
   DevDomain cur;
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
   const pf_domain_desc& g = d->desc;
-  const Layout& L = d->L;
-  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   if (phi || mu) {
-    std::vector<char> buf(L.copy_bytes);
-    PF_HIP(hipMemcpy(buf.data(), d->fields(cur.parity), L.copy_bytes, hipMemcpyDeviceToHost));
+    // each field as dense FP64, staged in the copy that does not hold the
+    // state (at least 8 bytes per cell and field), then to the host
+    double* stage = reinterpret_cast<double*>(d->fields(cur.parity ^ 1));
     for (int f = 0; f < NFIELD; ++f) {
       double* dstf = f < NP ? (phi ? phi + (size_t)f * n : nullptr)
                             : (mu ? mu + (size_t)(f - NP) * n : nullptr);
       if (!dstf) continue;
-      for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y) {
-          double* row = dstf + ((size_t)z * g.ny + y) * g.nx;
-          const size_t o = (size_t)f * L.fstride + (size_t)z * L.plane + (size_t)y * L.pitch;
-          if (g.prec == PF_FP64) {
-            std::memcpy(row, buf.data() + o * 8, sizeof(double) * g.nx);
-          } else {
-            const float* s = reinterpret_cast<const float*>(buf.data()) + o;
-            for (int x = 0; x < g.nx; ++x) row[x] = (double)s[x];
-          }
-        }
+      PF_HIP(launch_field_pack(d->dev, g.prec, n, cur.parity, f, stage, d->stream));
+      PF_HIP(hipMemcpyAsync(dstf, stage, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
+                            d->stream));
     }
+    // the staging covered the ghost planes of that copy: restore them; the
+    // copy no longer holds the chunks the bulk shortcut may take for equal
+    // in both copies: clear that mark from the current copy's flags (they
+    // still describe the current copy, which is unchanged)
+    if (d->host.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
+    PF_HIP(launch_drop_same(reinterpret_cast<uint8_t*>(d->base + d->L.off_pflag +
+                                                       cur.parity * d->L.pflag_bytes),
+                            (int64_t)d->L.pflag_bytes, d->stream));
+    PF_HIP(hipStreamSynchronize(d->stream));
   }
   if (diag) {
     const double t = (double)cur.step * d->dt;
@@ -726,7 +722,7 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
     diag->nonfinite = (int64_t)v[9];
     diag->window_shifts = cur.shifts;
     uint32_t words[kCountWords];
-    PF_HIP(hipMemcpy(words, d->base + L.off_jfree + sizeof(uint32_t) * (size_t)count_base(d->T.blocks()),
+    PF_HIP(hipMemcpy(words, d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)count_base(d->T.blocks()),
                      sizeof(words), hipMemcpyDeviceToHost));
     uint32_t counts[kCountKinds] = {};
     for (int k = 0; k < kCountKinds; ++k)
@@ -818,10 +814,11 @@ pf_status pf_checkpoint_save(pf_domain* d, const char* path) {
   st = write_all();
   // the staging block covered the ghost planes of that copy: restore them
   // whatever the outcome of the write; the copy no longer holds the chunks
-  // the bulk shortcut may take for equal in both copies: withdraw the flags
+  // the bulk shortcut may take for equal in both copies: clear that mark
   if (d->host.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
-  PF_HIP(hipMemsetAsync(reinterpret_cast<char*>(d->dev) + offsetof(DevDomain, pflag_ok), 0,
-                        sizeof(DevDomain::pflag_ok), d->stream));
+  PF_HIP(launch_drop_same(reinterpret_cast<uint8_t*>(d->base + d->L.off_pflag +
+                                                     cur.parity * d->L.pflag_bytes),
+                          (int64_t)d->L.pflag_bytes, d->stream));
   PF_HIP(hipStreamSynchronize(d->stream));
   return st;
 }

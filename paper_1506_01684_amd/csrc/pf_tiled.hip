@@ -1461,6 +1461,20 @@ __global__ __launch_bounds__(kTileThreads) void mu_light_f64(DevDomain* const* d
 
 // --------------------------------------------------------------- launches
 
+// The copy that does not hold the state has been overwritten (staging of a
+// host read or a checkpoint): no chunk is held by both copies any more.
+__global__ __launch_bounds__(256) void drop_same_kernel(uint8_t* flags, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = (uint8_t)(flags[i] & ~kSame);
+}
+
+hipError_t launch_drop_same(uint8_t* flags, int64_t n, hipStream_t s) {
+  const int64_t b = (n + 255) / 256;
+  drop_same_kernel<<<(int)(b < 1024 ? (b > 0 ? b : 1) : 1024), 256, 0, s>>>(flags, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
   const int grid = L.total;
   if (prec == 0)

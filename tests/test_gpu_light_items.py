@@ -146,6 +146,35 @@ def test_bulk_skip_survives_a_checkpoint_save():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("prec,top_bc", [("fp64", 0), ("fp32", 1)])
+def test_bulk_skip_survives_host_reads(prec, top_bc):
+    """pf_read_fields stages each field in the copy that does not hold the
+    state, which the bulk shortcut may take for equal to the current one:
+    reading the fields to the host between steps, then stepping on, equals
+    the shortcuts-off run bitwise (with a Dirichlet top too, whose ghost
+    planes the staging covers), and each read equals the other run's."""
+    shape = (96, 24, 70)
+    p = pfinputs.p0_params(solid_height=10)
+    p["top_bc"] = top_bc
+    p["dt"] = oracle.default_dt(p, shape)
+    out = {}
+    for sc in (0, 1):
+        q = dict(p, shortcuts=sc)
+        d = gpu_domain(shape, q, prec, 1, voronoi=(4, 7, 10))
+        reads = []
+        for n in (6, 1, 4):
+            d.step(n)
+            reads.append(d.read())
+        out[sc] = (reads, d.diagnostics())
+        d.close()
+    (ra, da), (rb, _) = out[1], out[0]
+    log(f"host reads {prec} top_bc={top_bc}: fixed items {da['fixed_items']}, "
+        f"copied {da['copied_items']}")
+    assert da["fixed_items"] > 0
+    for a, b in zip(ra, rb):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def _chunk_layout(shape, prec):
     """Tile and z chunk of the tiled sweeps (the rule the library applies:
     FP64 tiles are always 32x8, FP32 tiles 64x4 unless nx < 48)."""

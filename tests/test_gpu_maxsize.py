@@ -6,8 +6,7 @@ layout rejects anything larger (tests/test_abi.py).  This test runs a domain
 whose planes take 2^32 - 1024 bytes, so that the offsets of its last rows
 lie just below 2^32 and those past the middle above 2^31: 1 x 33554424 x 16
 cells in FP64 (16 doubles = one 128-byte row), about 103 GB of HBM for both
-copies and 78 GB of host memory for the staging of pf_init_fields and
-pf_read_fields.
+copies and 26 GB of host memory for each of the input and output arrays.
 
 The state is periodic in y with period 8 (a smooth mixed state of an 8-row
 domain, repeated 4194303 times), so after two steps every 8-row block must
