@@ -316,17 +316,21 @@ __device__ __forceinline__ bool item_light(const DD& d, const CTX& X) {
 }
 
 // jsel < 0: every item; 0: items that need the anti-trapping current;
-// 1: items that do not.
+// 1: items that do not.  skip: items whose word has any of these bits set
+// this step (taken by a kernel launched before) are passed over before
+// anything else of them is read, so that a launch whose items all went
+// elsewhere costs little more than one word per work group.
 template <typename R>
 __device__ __forceinline__ bool item_setup(DevDomain* const* doms, const int32_t* first,
                                            int ndom, int item, int t, ItemCtx<R>& X,
-                                           int jsel = -1) {
+                                           int jsel = -1, uint32_t skip = 0) {
   const int di = find_domain(first, ndom, item);
   const PF_CONST DevDomain& d = domain_at(doms, di);
   if (!d.active) return false;  // uniform over the work group
   const int local = item - first_item(first, di);
   X.dw = to_const(doms)[di];
   X.jf = static_cast<uint32_t*>(d.jfree) + local;
+  if (skip && (*to_const(X.jf) & skip)) return false;  // uniform
   X.jc = static_cast<uint32_t*>(d.jfree) + count_base(d.nitems);
   X.slot = local % kCountSlots;
   X.local = local;
@@ -504,7 +508,12 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     ItemCtx<R> X;
-    if (!item_setup(doms, first, ndom, item, t, X)) continue;
+    // chunks copied unchanged by phi_bulk_kernel (launched just before):
+    // FP64 passes them over before the tile is set up (a launch with every
+    // chunk kept, as on an all-liquid domain, then takes 16 instead of
+    // 22 us on 256x256x512), FP32 after it (the early test cost the FP32
+    // anisotropic sweep 0.4%)
+    if (!item_setup(doms, first, ndom, item, t, X, -1, sizeof(R) == 8 ? kBulkDone : 0u)) continue;
     const TileGeo& G = X.G;
     const Geo& g = X.g;
     const auto& P = kparams<R>(*X.dp);
@@ -516,7 +525,6 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
     const PF_CONST DevDomain& dd = *X.dp;
     const ChunkId cid = chunk_id(dd, G);
 
-    // chunks copied unchanged by phi_bulk_kernel (launched just before)
     if (*to_const(X.jf) & kBulkDone) continue;
     // pure phase of this thread's outputs so far (-2: none, -1: mixed), and
     // of its outputs on the first and last plane: bytes 0, 1, 2 hold each + 2
