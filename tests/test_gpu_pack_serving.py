@@ -53,12 +53,17 @@ def test_pack_matches_single_domain_bitwise(prec):
         pk.add(d, w["steps"])
         doms.append(d)
     longest = max(w["steps"] for w in ws)
-    # uneven rounds; every member idles once its own steps are done
+    # uneven rounds; every member idles once its own steps are done; the
+    # fields of some members are read to the host between rounds (staged in
+    # their second copy), which must not change what follows
     done = 0
-    for r in (3, 1, 7, longest):
+    for i, r in enumerate((3, 1, 7, longest)):
         fin = pk.step(r, count_finished=True)
         done += r
         assert fin == sum(w["steps"] <= done for w in ws)
+        if i < 2:
+            for d in doms[i::3]:
+                d.read()
     for w, d, a in zip(ws, doms, alone):
         assert pk.remaining(d) == 0
         assert d.step_index == w["steps"]
