@@ -577,15 +577,23 @@ def run_cpu_baseline(workload: str, budget_s: float = 20.0) -> dict:
         el = time.perf_counter() - t0
         if el * (n + 1) / n > budget_s:
             break
-    cpu = "unknown"
+    # the host CPU as /proc/cpuinfo describes its first processor (a
+    # virtual machine may report only the vendor's product line by name)
+    host = {"cpu": "unknown"}
+    keys = {"model name": "cpu", "cpu family": "family", "model": "model", "stepping": "stepping",
+            "cpu MHz": "mhz", "cache size": "cache"}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
+                if not line.strip():
                     break
+                k, _, v = line.partition(":")
+                if k.strip() in keys:
+                    host[keys[k.strip()]] = v.strip()
     except OSError:
         pass
+    host["nproc"] = os.cpu_count()
+    host["usable_cpus"] = len(os.sched_getaffinity(0))
     # the small workload in full (100 steps), on one thread and on all
     w1 = pfinputs.workload("c1")
     s1 = w1["shape"]
@@ -605,7 +613,7 @@ def run_cpu_baseline(workload: str, budget_s: float = 20.0) -> dict:
             "workload": f"{s1[2]}x{s1[1]}x{s1[0]} FP64, 100 steps from its Voronoi state",
             "one_thread_mlups": round(c1[1], 3), "all_threads_mlups": round(c1[threads], 3),
             "threads": threads},
-        "host": {"cpu": cpu, "nproc": os.cpu_count()},
+        "host": host,
     }
 
 
