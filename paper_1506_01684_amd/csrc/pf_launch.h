@@ -16,7 +16,9 @@ struct LaunchSet {
   const int32_t* first;
   int32_t ndom;
   int32_t total;
-  int32_t max_nz;  // largest nz among the domains (prologue loop bound)
+  // one domain: its per-item words (the sweeps' classification), so that a
+  // work group can test its item with one load; a pack: null
+  const uint32_t* words;
 };
 
 // Threads per work group of the sweeps (tile tx * ty).

@@ -211,7 +211,7 @@ struct pf_domain {
     s.first = dev_first;
     s.ndom = 1;
     s.total = T.blocks();
-    s.max_nz = desc.nz;
+    s.words = reinterpret_cast<const uint32_t*>(base + L.off_jfree);
     return s;
   }
 };
@@ -1006,7 +1006,7 @@ struct pf_pack {
   std::vector<pf_domain*> members;
   DevDomain** dev_ptrs = nullptr;
   int32_t* dev_first = nullptr;
-  int32_t total = 0, max_nz = 0;
+  int32_t total = 0;
   bool any_aniso = false;
   bool any_window = false;
   hipGraph_t graph = nullptr;
@@ -1029,13 +1029,11 @@ pf_status rebuild_pack(pf_pack* pk) {
   std::vector<int32_t> first(1, 0);
   pk->any_aniso = false;
   pk->any_window = false;
-  pk->max_nz = 0;
   for (pf_domain* d : pk->members) {
     ptrs.push_back(d->dev);
     first.push_back(first.back() + d->T.blocks());
     pk->any_aniso |= d->aniso;
     pk->any_window |= d->host.window_z > 0;
-    pk->max_nz = std::max(pk->max_nz, d->desc.nz);
   }
   pk->total = first.back();
   if (!ptrs.empty()) {
@@ -1052,7 +1050,7 @@ pf_status rebuild_pack(pf_pack* pk) {
     s.first = pk->dev_first;
     s.ndom = (int32_t)ptrs.size();
     s.total = pk->total;
-    s.max_nz = pk->max_nz;
+    s.words = nullptr;
     const int var = g_variant.load();
     PF_HIP(hipStreamBeginCapture(pk->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_prologue(s, pk->prec, pk->stream);

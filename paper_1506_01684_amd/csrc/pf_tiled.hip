@@ -494,7 +494,7 @@ __device__ __forceinline__ int wave_pure_phase(int po) {
 
 template <typename R, bool ANISO>
 __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int32_t* first,
-                                               int ndom, int total) {
+                                               int ndom, int total, const uint32_t* words) {
   constexpr int NSLOT = ANISO ? 3 : 1;
   constexpr int AHEAD = ANISO ? 2 : 1;  // plane loaded during iteration k: k + AHEAD
   __shared__ LdsPhi<R, NSLOT> s_phi;
@@ -507,6 +507,9 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
   const int wave = t >> 6, lane = t & 63;
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // a single domain's launch passes its item words: a chunk the bulk
+    // kernel kept is passed over after one load
+    if (words && (to_const(words)[item] & kBulkDone)) continue;
     ItemCtx<R> X;
     // chunks copied unchanged by phi_bulk_kernel (launched just before):
     // FP64 passes them over before the tile is set up (a launch with every
@@ -734,22 +737,22 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
 // SIMD (it needs 98 otherwise, which allows four).
 __global__ __launch_bounds__(kTileThreads) void phi_tiled_f64(DevDomain* const* doms,
                                                               const int32_t* first, int ndom,
-                                                              int total) {
-  phi_tiled_body<double, false>(doms, first, ndom, total);
+                                                              int total, const uint32_t* words) {
+  phi_tiled_body<double, false>(doms, first, ndom, total, words);
 }
 __global__ __launch_bounds__(kTileThreads) void phi_tiled_f64_aniso(DevDomain* const* doms,
                                                                     const int32_t* first, int ndom,
-                                                                    int total) {
-  phi_tiled_body<double, true>(doms, first, ndom, total);
+                                                                    int total, const uint32_t* words) {
+  phi_tiled_body<double, true>(doms, first, ndom, total, words);
 }
 __global__ __launch_bounds__(kTileThreads) void phi_tiled_f32(DevDomain* const* doms,
                                                               const int32_t* first, int ndom,
-                                                              int total) {
-  phi_tiled_body<float, false>(doms, first, ndom, total);
+                                                              int total, const uint32_t* words) {
+  phi_tiled_body<float, false>(doms, first, ndom, total, words);
 }
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(5))) void
-phi_tiled_f32_aniso(DevDomain* const* doms, const int32_t* first, int ndom, int total) {
-  phi_tiled_body<float, true>(doms, first, ndom, total);
+phi_tiled_f32_aniso(DevDomain* const* doms, const int32_t* first, int ndom, int total, const uint32_t* words) {
+  phi_tiled_body<float, true>(doms, first, ndom, total, words);
 }
 
 // Bulk shortcut of the phi-sweep, launched before it over the same items:
@@ -826,7 +829,7 @@ __device__ __forceinline__ void face_dphi(const V4<R>& L1, const V4<R>& U1, cons
 
 template <typename R>
 __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int32_t* first, int ndom,
-                                              int total) {
+                                              int total, const uint32_t* words) {
   constexpr int NSLOT = 3, AHEAD = 2;
   __shared__ LdsPhi<R, NSLOT> s_phi;
   __shared__ LdsMu<R> s_mu;         // mu^n of plane k
@@ -837,6 +840,10 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
   const int wave = t >> 6, lane = t & 63;
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // a single domain's launch passes its item words: an FP64 item the
+    // pure-item launch took is passed over after one load (in FP32 the extra
+    // load ahead of every item's set-up cost more than it saved: c3 +0.8%)
+    if (sizeof(R) == 8 && words && (to_const(words)[item] & kMuPure)) continue;
     ItemCtx<R> X;
     // FP64: the items that need the anti-trapping current (mu_light_f64
     // takes the rest); FP32: every item
@@ -1121,12 +1128,12 @@ __device__ __forceinline__ void mu_tiled_body(DevDomain* const* doms, const int3
 
 // The FP32 instance is held to 128 VGPRs so that four waves fit per SIMD.
 __global__ __launch_bounds__(kTileThreads) void mu_tiled_f64(DevDomain* const* doms, const int32_t* first,
-                                                             int ndom, int total) {
-  mu_tiled_body<double>(doms, first, ndom, total);
+                                                             int ndom, int total, const uint32_t* words) {
+  mu_tiled_body<double>(doms, first, ndom, total, words);
 }
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(4))) void mu_tiled_f32(
-    DevDomain* const* doms, const int32_t* first, int ndom, int total) {
-  mu_tiled_body<float>(doms, first, ndom, total);
+    DevDomain* const* doms, const int32_t* first, int ndom, int total, const uint32_t* words) {
+  mu_tiled_body<float>(doms, first, ndom, total, words);
 }
 
 // mu-sweep of the items whose faces carry no anti-trapping current
@@ -1493,14 +1500,14 @@ hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_
         L.doms, L.first, L.ndom, L.total);
   if (prec == 0) {
     if (aniso)
-      phi_tiled_f64_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f64_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
     else
-      phi_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
   } else {
     if (aniso)
-      phi_tiled_f32_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f32_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
     else
-      phi_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+      phi_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
   }
   return hipGetLastError();
 }
@@ -1513,10 +1520,10 @@ hipError_t launch_mu_tiled(const LaunchSet& L, int prec, hipStream_t s) {
   const int grid = L.total;
   if (prec == 0) {
     mu_light_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
-    mu_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    mu_tiled_f64<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
   } else {
     mu_pure_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
-    mu_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total);
+    mu_tiled_f32<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
   }
   return hipGetLastError();
 }
