@@ -760,17 +760,52 @@ phi_tiled_f32_aniso(DevDomain* const* doms, const int32_t* first, int ndom, int 
 // and (FP64) the mu-sweep's classification are written, and its word is
 // marked kBulkDone so that the sweep passes it over; every other item's
 // word is cleared for the sweep to fill.
+// phi_bulk_kernel takes `per` consecutive items per wave, and the work
+// group adds the counts of its items to the step's counters once: an
+// increment of one word is serialised (about 12 ns each), and one per item
+// made the kernel wait on the counters (55 us for the 32768 items of a
+// 512x512x1024 FP32 domain).  More items per wave cut the increments
+// further but run the waves' tests one after another, so a launch takes
+// one item per wave until its waves would fill the chip more than once
+// (bulk_items_per_wave).
+constexpr int kBulkMaxPerWave = 4, kBulkFillWaves = 8192;
+inline int bulk_items_per_wave(int total) {
+  const int per = total / kBulkFillWaves;
+  return per < 1 ? 1 : (per > kBulkMaxPerWave ? kBulkMaxPerWave : per);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const* doms,
                                                                 const int32_t* first, int ndom,
-                                                                int total) {
-  // one item per wave: the test is a few dependent loads, so four items in
-  // flight per work group instead of one
+                                                                int total, int per) {
+  // the test is a few dependent loads, so each wave takes its own items
+  // (four waves' tests in flight per work group)
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // scalar
   const int lane = threadIdx.x & 63;
-  for (int item = blockIdx.x * kTileWaves + wave; item < total; item += gridDim.x * kTileWaves) {
+  // counts of this wave's items not yet added: fixed, copied, light, and
+  // the domain's counter words they belong to (uniform over the wave)
+  __shared__ uint32_t* s_jc[kTileWaves];
+  __shared__ uint32_t s_n[kTileWaves][3];
+  uint32_t* jc = nullptr;
+  int slot = 0;
+  uint32_t n[3] = {0u, 0u, 0u};
+  const auto flush = [&]() {
+    if (lane == 0 && jc) {
+      if (n[0]) atomicAdd(jc + count_word(kCountFixed, slot), n[0]);
+      if (n[1]) atomicAdd(jc + count_word(kCountCopied, slot), n[1]);
+      if (n[2]) atomicAdd(jc + count_word(kCountLight, slot), n[2]);
+    }
+    n[0] = n[1] = n[2] = 0u;
+  };
+  const int base = (blockIdx.x * kTileWaves + wave) * per;
+  for (int item = base; item < base + per && item < total; ++item) {
     ItemCtx<R> X;
     if (!item_setup(doms, first, ndom, item, lane, X)) continue;  // uniform over the wave
+    if (X.jc != jc) {  // another domain (a pack): add what the last one counted
+      flush();
+      jc = X.jc;
+      slot = X.slot;
+    }
     const auto& P = kparams<R>(*X.dp);
     const PF_CONST DevDomain& dd = *X.dp;
     const ChunkId cid = chunk_id(dd, X.G);
@@ -786,7 +821,7 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
     const bool same =
         to_const(static_cast<const uint8_t*>(dd.pflag[dd.cur_src]))[chunk_index(dd, cid)] & kSame;
     if (!same) {
-      if (lane == 0) atomicAdd(X.jc + count_word(kCountCopied, X.slot), 1u);
+      ++n[1];
 #pragma unroll 1
       for (int c = lane; c < kTileThreads; c += 64) {
         const TileGeo Gc = make_tile<R>(dd, X.local, c);
@@ -799,19 +834,44 @@ __global__ __launch_bounds__(kTileThreads) void phi_bulk_kernel(DevDomain* const
         }
       }
     }
+    ++n[0];
+    uint32_t w = 0;
+    if constexpr (sizeof(R) == 8) {  // the mu-sweep's classification (item_jfree)
+      const uint32_t b = P.mu_frozen ? 0u : (!P.antitrap ? 3u : (fixed == LQ ? 2u : 1u));
+      w = b * 0x01010101u;
+      if (item_jfree(w)) ++n[2];
+    }
     if (lane == 0) {
       static_cast<uint8_t*>(dd.pflag[dd.cur_src ^ 1])[chunk_index(dd, cid)] =
           (uint8_t)(fixed | kSame);
       static_cast<uint8_t*>(dd.pends[dd.cur_src ^ 1])[chunk_index(dd, cid)] = (uint8_t)(fixed << 4 | fixed);
       dd_mark_flags(dd, X.dw);
-      atomicAdd(X.jc + count_word(kCountFixed, X.slot), 1u);
-      uint32_t w = 0;
-      if constexpr (sizeof(R) == 8) {  // the mu-sweep's classification (item_jfree)
-        const uint32_t b = P.mu_frozen ? 0u : (!P.antitrap ? 3u : (fixed == LQ ? 2u : 1u));
-        w = b * 0x01010101u;
-        if (item_jfree(w)) atomicAdd(X.jc + count_word(kCountLight, X.slot), 1u);
-      }
       *to_global(X.jf) = w | kBulkDone;
+    }
+  }
+  // the waves of a work group that counted for one domain add their counts
+  // together, the others each their own
+  if (lane == 0) {
+    s_jc[wave] = jc;
+    s_n[wave][0] = n[0];
+    s_n[wave][1] = n[1];
+    s_n[wave][2] = n[2];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 0; v < kTileWaves; ++v) {
+      uint32_t* j = s_jc[v];
+      if (!j) continue;
+      uint32_t t[3] = {s_n[v][0], s_n[v][1], s_n[v][2]};
+      for (int u = v + 1; u < kTileWaves; ++u)
+        if (s_jc[u] == j) {
+          for (int q = 0; q < 3; ++q) t[q] += s_n[u][q];
+          s_jc[u] = nullptr;
+        }
+      const int sl = (int)(blockIdx.x % kCountSlots);
+      if (t[0]) atomicAdd(j + count_word(kCountFixed, sl), t[0]);
+      if (t[1]) atomicAdd(j + count_word(kCountCopied, sl), t[1]);
+      if (t[2]) atomicAdd(j + count_word(kCountLight, sl), t[2]);
     }
   }
 }
@@ -1492,12 +1552,13 @@ hipError_t launch_drop_same(uint8_t* flags, int64_t n, hipStream_t s) {
 
 hipError_t launch_phi_tiled(const LaunchSet& L, int prec, bool aniso, hipStream_t s) {
   const int grid = L.total;
+  const int per = bulk_items_per_wave(L.total);
   if (prec == 0)
-    phi_bulk_kernel<double><<<(grid + kTileWaves - 1) / kTileWaves, kTileThreads, 0, s>>>(
-        L.doms, L.first, L.ndom, L.total);
+    phi_bulk_kernel<double><<<(grid + per * kTileWaves - 1) / (per * kTileWaves), kTileThreads, 0, s>>>(
+        L.doms, L.first, L.ndom, L.total, per);
   else
-    phi_bulk_kernel<float><<<(grid + kTileWaves - 1) / kTileWaves, kTileThreads, 0, s>>>(
-        L.doms, L.first, L.ndom, L.total);
+    phi_bulk_kernel<float><<<(grid + per * kTileWaves - 1) / (per * kTileWaves), kTileThreads, 0, s>>>(
+        L.doms, L.first, L.ndom, L.total, per);
   if (prec == 0) {
     if (aniso)
       phi_tiled_f64_aniso<<<grid, kTileThreads, 0, s>>>(L.doms, L.first, L.ndom, L.total, L.words);
