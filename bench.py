@@ -669,8 +669,8 @@ def main():
         print(json.dumps({"metric": "served-solve latency (p50/p99)", "serving": r}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(multi-GPU sharding is described, not built)", file=sys.stderr)
+        print("bench.py: this benchmark runs on one GPU; --gpus must be 1 "
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     main_run = run_gpu(args.workload, args.steps, args.warmup, args.variant, args.shortcuts)
