@@ -27,7 +27,9 @@
 //     take a lighter body that stages one phi^n plane and no phi^{n+1}
 //     neighbours (mu_bulk_item).
 // The last two run in one FP64 launch (mu_light_f64) before the full
-// kernel, which passes their items over.
+// kernel, which passes their items over.  A single domain's launch also
+// passes the per-item words, so that a work group whose item an earlier
+// launch of the step took leaves after one load.
 // In the phi-sweep a face enters its two cells' A_a through two shares
 // (face_pq): the one for the cell below the face stays in the registers of
 // the thread that evaluated it, only the one for the cell above goes
@@ -511,11 +513,9 @@ __device__ __forceinline__ void phi_tiled_body(DevDomain* const* doms, const int
     // kernel kept is passed over after one load
     if (words && (to_const(words)[item] & kBulkDone)) continue;
     ItemCtx<R> X;
-    // chunks copied unchanged by phi_bulk_kernel (launched just before):
-    // FP64 passes them over before the tile is set up (a launch with every
-    // chunk kept, as on an all-liquid domain, then takes 16 instead of
-    // 22 us on 256x256x512), FP32 after it (the early test cost the FP32
-    // anisotropic sweep 0.4%)
+    // in a pack (no item words), the chunks copied unchanged by
+    // phi_bulk_kernel: FP64 passes them over before the tile is set up,
+    // FP32 after it (the early test cost the FP32 anisotropic sweep 0.4%)
     if (!item_setup(doms, first, ndom, item, t, X, -1, sizeof(R) == 8 ? kBulkDone : 0u)) continue;
     const TileGeo& G = X.G;
     const Geo& g = X.g;
