@@ -213,7 +213,10 @@ pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound);
  * HOST: copy (and for FP32 round) the caller's arrays, phi[4][nz][ny][nx]
  * and mu[2][nz][ny][nx] (host memory, read only, still owned by the
  * caller); each field passes through the domain's second field copy on the
- * device, so no memory is allocated.  Synchronises. */
+ * device, so no memory is allocated.  Synchronises.  Errors: INVALID_ARG
+ * (unknown kind, nseeds or solid_height < 0, null HOST arrays) leaves the
+ * domain as it was; DEVICE leaves it without fields (step and read calls
+ * return STATE until it is initialised again). */
 pf_status pf_init_fields(pf_domain* d, const pf_init* init);
 
 /* Resume from a checkpoint (Sec. 3.2 checkpointing): the next step is

@@ -530,6 +530,15 @@ pf_status pf_get_dt(const pf_domain* d, double* dt, double* bound) {
 pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   if (!d || !in) return fail(PF_ERR_INVALID_ARG, "null argument");
   if (d->pack) return fail(PF_ERR_STATE, "domain is a pack member");
+  // arguments first: a refused call leaves the domain as it was
+  if (in->kind == PF_INIT_VORONOI) {
+    if (in->nseeds < 0 || in->solid_height < 0)
+      return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
+  } else if (in->kind == PF_INIT_HOST) {
+    if (!in->phi || !in->mu) return fail(PF_ERR_INVALID_ARG, "HOST init needs phi and mu");
+  } else {
+    return fail(PF_ERR_INVALID_ARG, "unknown init kind");
+  }
   const pf_domain_desc& g = d->desc;
   const Layout& L = d->L;
   pf_status st;
@@ -539,6 +548,9 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
     DevDomain cur;
     if ((st = fetch_state(d, cur)) != PF_OK) return st;
   }
+  // until the new fields are complete the domain holds no usable state (a
+  // failed call leaves it so: stepping or reading it is refused)
+  d->fields_set = false;
   h.step = 0;
   h.parity = 0;
   h.shifts = 0;
@@ -549,8 +561,6 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
   PF_HIP(hipMemsetAsync(d->base + d->L.off_jfree + sizeof(uint32_t) * (size_t)count_base(d->T.blocks()),
                         0, sizeof(uint32_t) * kCountWords, d->stream));
   if (in->kind == PF_INIT_VORONOI) {
-    if (in->nseeds < 0 || in->solid_height < 0)
-      return fail(PF_ERR_INVALID_ARG, "nseeds and solid_height must be >= 0");
     std::vector<int8_t> map;
     voronoi_columns(g.nx, g.ny, in->seed, in->nseeds, map);
     int8_t* dmap = reinterpret_cast<int8_t*>(d->base + L.off_map);
@@ -558,8 +568,7 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
     PF_HIP(launch_fill(d->dev, g.prec, g.nx, g.ny, g.nz, dmap, in->solid_height, in->mu_init[0],
                        in->mu_init[1], d->stream));
     PF_HIP(hipStreamSynchronize(d->stream));
-  } else if (in->kind == PF_INIT_HOST) {
-    if (!in->phi || !in->mu) return fail(PF_ERR_INVALID_ARG, "HOST init needs phi and mu");
+  } else {  // PF_INIT_HOST
     // each field goes to copy 1 as dense FP64 (a copy holds at least
     // 8 bytes per cell and field: six fields of at least 4 bytes), and a
     // kernel rounds it into copy 0; padding and the ghost planes of copy 0
@@ -574,8 +583,6 @@ pf_status pf_init_fields(pf_domain* d, const pf_init* in) {
       PF_HIP(launch_field_unpack(d->dev, g.prec, n, 0, f, stage, d->stream));
     }
     PF_HIP(hipStreamSynchronize(d->stream));
-  } else {
-    return fail(PF_ERR_INVALID_ARG, "unknown init kind");
   }
   if (h.top_bc) {
     PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
@@ -687,25 +694,34 @@ pf_status pf_read_fields(pf_domain* d, double* phi, double* mu, pf_diag* diag) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   if (phi || mu) {
     // each field as dense FP64, staged in the copy that does not hold the
-    // state (at least 8 bytes per cell and field), then to the host
-    double* stage = reinterpret_cast<double*>(d->fields(cur.parity ^ 1));
-    for (int f = 0; f < NFIELD; ++f) {
-      double* dstf = f < NP ? (phi ? phi + (size_t)f * n : nullptr)
-                            : (mu ? mu + (size_t)(f - NP) * n : nullptr);
-      if (!dstf) continue;
-      PF_HIP(launch_field_pack(d->dev, g.prec, n, cur.parity, f, stage, d->stream));
-      PF_HIP(hipMemcpyAsync(dstf, stage, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
-                            d->stream));
-    }
-    // the staging covered the ghost planes of that copy: restore them; the
-    // copy no longer holds the chunks the bulk shortcut may take for equal
-    // in both copies: clear that mark from the current copy's flags (they
-    // still describe the current copy, which is unchanged)
-    if (d->host.top_bc) PF_HIP(launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream));
+    // state (at least 8 bytes per cell and field), then to the host.  That
+    // copy will no longer hold the chunks the bulk shortcut may take for
+    // equal in both copies: first clear that mark from the current copy's
+    // flags (they still describe the current copy, which is unchanged)
     PF_HIP(launch_drop_same(reinterpret_cast<uint8_t*>(d->base + d->L.off_pflag +
                                                        cur.parity * d->L.pflag_bytes),
                             (int64_t)d->L.pflag_bytes, d->stream));
-    PF_HIP(hipStreamSynchronize(d->stream));
+    double* stage = reinterpret_cast<double*>(d->fields(cur.parity ^ 1));
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < NFIELD && e == hipSuccess; ++f) {
+      double* dstf = f < NP ? (phi ? phi + (size_t)f * n : nullptr)
+                            : (mu ? mu + (size_t)(f - NP) * n : nullptr);
+      if (!dstf) continue;
+      e = launch_field_pack(d->dev, g.prec, n, cur.parity, f, stage, d->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dstf, stage, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
+                           d->stream);
+    }
+    // the staging covered the ghost planes of that copy: restore them,
+    // whatever the outcome of the copies
+    if (d->host.top_bc) {
+      const hipError_t eg = launch_ghost(d->dev, g.prec, g.nx, g.ny, d->stream);
+      if (e == hipSuccess) e = eg;
+    }
+    const hipError_t es = hipStreamSynchronize(d->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess)
+      return fail(PF_ERR_DEVICE, std::string("reading the fields: ") + hipGetErrorString(e));
   }
   if (diag) {
     const double t = (double)cur.step * d->dt;

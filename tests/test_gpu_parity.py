@@ -204,6 +204,19 @@ def test_error_paths():
     d.close()
     with pytest.raises(pf.PfError):
         pf.Domain((0, 4, 4))
+    # a refused initialisation leaves the domain as it was
+    d = pf.Domain(shape, "fp64")
+    d.set_params(p)
+    d.init_voronoi(3, 4, 2)
+    d.step(3)
+    before = d.read()
+    with pytest.raises(pf.PfError) as e:
+        d.init_voronoi(3, -1, 2)
+    assert "INVALID_ARG" in str(e.value)
+    assert d.step_index == 3
+    after = d.read()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    d.close()
 
 
 @pytest.mark.parametrize("prec,aniso,nucleating", [("fp64", False, False), ("fp32", True, False),
