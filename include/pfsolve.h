@@ -292,7 +292,8 @@ pf_status pf_checkpoint_save(pf_domain* d, const char* path);
  * argument, a header that is not a checkpoint or a size mismatch, STATE
  * before pf_set_params or for a pack member, IO if the file cannot be
  * opened or its length is not header + 24 bytes per cell (the state is then
- * untouched) or a read fails part way (the state is then undefined until
+ * untouched) or a read fails part way; after a read or DEVICE error part
+ * way the domain holds no state (step and read calls return STATE until
  * the next successful load or pf_init_fields). */
 pf_status pf_checkpoint_load(pf_domain* d, const char* path);
 

@@ -862,7 +862,10 @@ pf_status pf_checkpoint_load(pf_domain* d, const char* path) {
   pf_status st;
   DevDomain cur;
   if ((st = fetch_state(d, cur)) != PF_OK) return st;
-  // read into copy 1, widen into copy 0, which then holds the state
+  // read into copy 1, widen into copy 0, which then holds the state; from
+  // the first write on, the old state may be gone: until the load has
+  // completed the domain holds no usable state (a failed load leaves it so)
+  d->fields_set = false;
   float* stage = reinterpret_cast<float*>(d->fields(1));
   const size_t total = sizeof(float) * NFIELD * (size_t)cells;
   std::vector<char> buf(std::min(total, kCkptChunk));
