@@ -1375,7 +1375,7 @@ constexpr int kPureAhead = 4;
 // The LDS of the pure items' body.
 template <typename R>
 struct PureLds {
-  LdsMu<R> m[2];            // mu^n of plane k with the halo ring, by plane parity
+  LdsMu<R> m[4];            // mu^n of planes k, k+1 with the halo ring, two pairs
   R cf[kMaxZc][kPureCoef];  // the item's plane coefficients, staged once (the
                             // table is too large for the scalar cache, and a
                             // scalar load per value and plane would put a round
@@ -1455,46 +1455,58 @@ __device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds
         Pzl[q] = mu_face_flux<R>(X.tab[kb].MpZ[a][q], mb[q], ro[0][q], inv_dx);
     }
     const int ox = G.lx + 1, oy = G.ly + 1;
+    // planes in pairs: both go to LDS before one barrier (the buffers of
+    // the pair before were consumed before the previous barrier)
+    static_assert(kPureAhead % 2 == 0, "pairs of ring slots");
+    const auto plane = [&](int k, const LdsMu<R>& sm, const R m[NM], const R up[NM]) {
+      if (!G.valid) return;
+      const R* cf = s_cf[k - z0];
+      const bool zf = g.zface(k);
+      R L[4][NM];
+      sm.get(G.ci(ox - 1, oy), L[0]);
+      sm.get(G.ci(ox + 1, oy), L[1]);
+      sm.get(G.ci(ox, oy - 1), L[2]);
+      sm.get(G.ci(ox, oy + 1), L[3]);
+#pragma unroll
+      for (int q = 0; q < NM; ++q) {
+        const R Mxy = cf[q];
+        const R fxl = mu_face_flux<R>(Mxy, L[0][q], m[q], inv_dx);
+        const R fxu = mu_face_flux<R>(Mxy, m[q], L[1][q], inv_dx);
+        const R fyl = mu_face_flux<R>(Mxy, L[2][q], m[q], inv_dx);
+        const R fyu = mu_face_flux<R>(Mxy, m[q], L[3][q], inv_dx);
+        const R Pzu = zf ? mu_face_flux<R>(cf[2 + q], m[q], up[q], inv_dx) : R(0);
+        R div = R(0);
+        div += fxu - fxl;
+        div += fyu - fyl;
+        div = (div + (Pzu - Pzl[q])) * inv_dx;
+        Pzl[q] = Pzu;
+        const R sq = mu_pure_src<R>(ha, cf[6 + q], cf[8 + q], m[q]);
+        stg<R>(dst.at(4 + q, k), G.own_b, mu_cell_out<R>(P, div, sq, cf[4 + q], m[q]));
+      }
+    };
     for (int k0 = z0; k0 < z1; k0 += kPureAhead) {
 #pragma unroll
-      for (int u = 0; u < kPureAhead; ++u) {
+      for (int u = 0; u < kPureAhead; u += 2) {
         const int k = k0 + u;
         if (k >= z1) break;  // uniform
-        LdsMu<R>& sm = s_m[k & 1];
-        // plane k into LDS; its own value and the one above in registers
-        const R m[NM] = {ro[u][0], ro[u][1]};
-        sm.put(G.own_c, m);
-        if (halo) sm.put(G.halo_c, rh[u]);
-        const int u1 = (u + 1) % kPureAhead;  // a constant once unrolled
-        const R up[NM] = {ro[u1][0], ro[u1][1]};
-        // slot u is free: plane k + kPureAhead
-        fetch(k + kPureAhead, ro[u], rh[u]);
-        __syncthreads();  // plane k visible (the buffer of plane k-2 was consumed)
-        if (G.valid) {
-          const R* cf = s_cf[k - z0];
-          const bool zf = g.zface(k);
-          R L[4][NM];
-          sm.get(G.ci(ox - 1, oy), L[0]);
-          sm.get(G.ci(ox + 1, oy), L[1]);
-          sm.get(G.ci(ox, oy - 1), L[2]);
-          sm.get(G.ci(ox, oy + 1), L[3]);
-#pragma unroll
-          for (int q = 0; q < NM; ++q) {
-            const R Mxy = cf[q];
-            const R fxl = mu_face_flux<R>(Mxy, L[0][q], m[q], inv_dx);
-            const R fxu = mu_face_flux<R>(Mxy, m[q], L[1][q], inv_dx);
-            const R fyl = mu_face_flux<R>(Mxy, L[2][q], m[q], inv_dx);
-            const R fyu = mu_face_flux<R>(Mxy, m[q], L[3][q], inv_dx);
-            const R Pzu = zf ? mu_face_flux<R>(cf[2 + q], m[q], up[q], inv_dx) : R(0);
-            R div = R(0);
-            div += fxu - fxl;
-            div += fyu - fyl;
-            div = (div + (Pzu - Pzl[q])) * inv_dx;
-            Pzl[q] = Pzu;
-            const R sq = mu_pure_src<R>(ha, cf[6 + q], cf[8 + q], m[q]);
-            stg<R>(dst.at(4 + q, k), G.own_b, mu_cell_out<R>(P, div, sq, cf[4 + q], m[q]));
-          }
+        const bool two = k + 1 < z1;  // uniform
+        // planes k and k+1 into LDS buffers u and u+1; their own values and
+        // the ones above in registers (a constant slot once unrolled)
+        const int u1 = u + 1, u2 = (u + 2) % kPureAhead;
+        const R m0[NM] = {ro[u][0], ro[u][1]}, m1[NM] = {ro[u1][0], ro[u1][1]};
+        const R up1[NM] = {ro[u2][0], ro[u2][1]};
+        s_m[u].put(G.own_c, m0);
+        if (halo) s_m[u].put(G.halo_c, rh[u]);
+        if (two) {
+          s_m[u1].put(G.own_c, m1);
+          if (halo) s_m[u1].put(G.halo_c, rh[u1]);
         }
+        // slots u and u+1 are free: planes k + kPureAhead and k + 1 + kPureAhead
+        fetch(k + kPureAhead, ro[u], rh[u]);
+        fetch(k + 1 + kPureAhead, ro[u1], rh[u1]);
+        __syncthreads();  // planes k and k+1 visible
+        plane(k, s_m[u], m0, m1);
+        if (two) plane(k + 1, s_m[u1], m1, up1);
       }
     }
   }
