@@ -1373,9 +1373,13 @@ __device__ __forceinline__ R pure_coef(const PF_CONST PlaneCoef<R>& C, int a, in
 constexpr int kPureAhead = 4;
 
 // The LDS of the pure items' body.
+// Planes of the pure-item body per barrier: FP64 two (four plane buffers
+// keep mu_light_f64's LDS within its light body's), FP32 four.
+template <typename R>
+constexpr int kPureGroup = sizeof(R) == 8 ? 2 : 4;
 template <typename R>
 struct PureLds {
-  LdsMu<R> m[4];            // mu^n of planes k, k+1 with the halo ring, two pairs
+  LdsMu<R> m[2 * kPureGroup<R>];  // mu^n with the halo ring, two groups of planes
   R cf[kMaxZc][kPureCoef];  // the item's plane coefficients, staged once (the
                             // table is too large for the scalar cache, and a
                             // scalar load per value and plane would put a round
@@ -1455,9 +1459,10 @@ __device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds
         Pzl[q] = mu_face_flux<R>(X.tab[kb].MpZ[a][q], mb[q], ro[0][q], inv_dx);
     }
     const int ox = G.lx + 1, oy = G.ly + 1;
-    // planes in pairs: both go to LDS before one barrier (the buffers of
-    // the pair before were consumed before the previous barrier)
-    static_assert(kPureAhead % 2 == 0, "pairs of ring slots");
+    // planes in groups of G: all go to LDS before one barrier (the buffers
+    // of the group before were consumed before the previous barrier)
+    constexpr int Gp = kPureGroup<R>;
+    static_assert(kPureAhead % Gp == 0, "groups of ring slots");
     const auto plane = [&](int k, const LdsMu<R>& sm, const R m[NM], const R up[NM]) {
       if (!G.valid) return;
       const R* cf = s_cf[k - z0];
@@ -1486,27 +1491,38 @@ __device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds
     };
     for (int k0 = z0; k0 < z1; k0 += kPureAhead) {
 #pragma unroll
-      for (int u = 0; u < kPureAhead; u += 2) {
+      for (int u = 0; u < kPureAhead; u += Gp) {
         const int k = k0 + u;
         if (k >= z1) break;  // uniform
-        const bool two = k + 1 < z1;  // uniform
-        // planes k and k+1 into LDS buffers u and u+1; their own values and
-        // the ones above in registers (a constant slot once unrolled)
-        const int u1 = u + 1, u2 = (u + 2) % kPureAhead;
-        const R m0[NM] = {ro[u][0], ro[u][1]}, m1[NM] = {ro[u1][0], ro[u1][1]};
-        const R up1[NM] = {ro[u2][0], ro[u2][1]};
-        s_m[u].put(G.own_c, m0);
-        if (halo) s_m[u].put(G.halo_c, rh[u]);
-        if (two) {
-          s_m[u1].put(G.own_c, m1);
-          if (halo) s_m[u1].put(G.halo_c, rh[u1]);
+        // buffers of this group: the two halves alternate from group to group
+        LdsMu<R>* sb = s_m + (((k - z0) / Gp) & 1) * Gp;
+        // planes k .. k+Gp-1 into LDS; their own values and the ones above
+        // in registers (constant slots once unrolled)
+        R mv[Gp + 1][NM];
+#pragma unroll
+        for (int j = 0; j < Gp; ++j) {
+          mv[j][0] = ro[u + j][0];
+          mv[j][1] = ro[u + j][1];
         }
-        // slots u and u+1 are free: planes k + kPureAhead and k + 1 + kPureAhead
-        fetch(k + kPureAhead, ro[u], rh[u]);
-        fetch(k + 1 + kPureAhead, ro[u1], rh[u1]);
-        __syncthreads();  // planes k and k+1 visible
-        plane(k, s_m[u], m0, m1);
-        if (two) plane(k + 1, s_m[u1], m1, up1);
+#pragma unroll
+        for (int j = 0; j < Gp; ++j) {
+          if (k + j >= z1) break;  // uniform
+          sb[j].put(G.own_c, mv[j]);
+          if (halo) sb[j].put(G.halo_c, rh[u + j]);
+        }
+        // the group's slots are free: planes kPureAhead further on
+#pragma unroll
+        for (int j = 0; j < Gp; ++j) fetch(k + j + kPureAhead, ro[u + j], rh[u + j]);
+        // plane k+Gp, above the group's last plane: still in the ring when
+        // the group is shorter than the ring, else the load just issued
+        mv[Gp][0] = ro[(u + Gp) % kPureAhead][0];
+        mv[Gp][1] = ro[(u + Gp) % kPureAhead][1];
+        __syncthreads();  // the group's planes visible
+#pragma unroll
+        for (int j = 0; j < Gp; ++j) {
+          if (k + j >= z1) break;  // uniform
+          plane(k + j, sb[j], mv[j], mv[j + 1]);
+        }
       }
     }
   }
