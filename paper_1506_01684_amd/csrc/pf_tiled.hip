@@ -1459,8 +1459,9 @@ __device__ __forceinline__ void mu_pure_item(const ItemCtx<R>& X, int a, PureLds
         Pzl[q] = mu_face_flux<R>(X.tab[kb].MpZ[a][q], mb[q], ro[0][q], inv_dx);
     }
     const int ox = G.lx + 1, oy = G.ly + 1;
-    // planes in groups of G: all go to LDS before one barrier (the buffers
-    // of the group before were consumed before the previous barrier)
+    // planes in groups of Gp: all go to LDS before one barrier; the groups
+    // alternate between two halves of the buffers, so a group writes the
+    // half whose reads (two groups back) ended before the last barrier
     constexpr int Gp = kPureGroup<R>;
     static_assert(kPureAhead % Gp == 0, "groups of ring slots");
     const auto plane = [&](int k, const LdsMu<R>& sm, const R m[NM], const R up[NM]) {
